@@ -1,0 +1,195 @@
+"""Seeded synthetic workload generators.
+
+This module is shared by the tests, the benchmark and the oracle's callers.  It
+draws random inputs only: images, residual frames, transform-unit layouts,
+request traces.  It contains none of the transform arithmetic, so neither the
+HIP library nor the oracle depends on the other through it.
+
+Workloads (all seeded with NumPy's PCG64):
+
+* 2D separable first-order Markov (AR(1)) images.  The paper models images as
+  a first-order Markov process with covariance rho^|m-n| (section 4.1, coding
+  gain); its 30 test images (section 5.1) are not available, so this field
+  stands in for them.
+* Laplacian prediction residuals (int16) with 4:2:0 chroma planes, standing in
+  for the video sequences of section 6.2.
+* HEVC-style quadtree partitions of an image into 8/16/32 transform units.
+* Log-normal image sizes and Poisson arrival traces for the batched and
+  served forms.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.signal import lfilter
+
+__all__ = [
+    "rng_for",
+    "ar1_field",
+    "ar1_image",
+    "ar1_batch_image",
+    "laplace_residual",
+    "residual_frame_planes",
+    "quadtree_tus",
+    "ragged_sizes",
+    "poisson_arrivals",
+    "serving_requests",
+]
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _round_half_away(x: np.ndarray) -> np.ndarray:
+    # data quantisation of the synthetic field to integer grey levels
+    return np.sign(x) * np.floor(np.abs(x) + 0.5)
+
+
+def _ar1_filter(w: np.ndarray, rho: float, axis: int) -> np.ndarray:
+    """Stationary unit-variance AR(1) recursion along ``axis``.
+
+    y[0] = w[0];  y[n] = rho*y[n-1] + sqrt(1-rho^2)*w[n].
+    """
+    c = np.sqrt(1.0 - rho * rho)
+    w = np.array(w, dtype=np.float64, copy=True)
+    idx = [slice(None)] * w.ndim
+    idx[axis] = 0
+    # scale the first sample so that the filter output starts at y[0] = w[0]
+    w[tuple(idx)] /= c
+    return lfilter([c], [1.0, -rho], w, axis=axis)
+
+
+def ar1_field(h: int, w: int, rho: float, rng: np.random.Generator) -> np.ndarray:
+    """Unit-variance 2D separable AR(1) Gaussian field (float64, h x w)."""
+    white = rng.standard_normal((h, w))
+    y = _ar1_filter(white, rho, axis=1)
+    y = _ar1_filter(y, rho, axis=0)
+    return y
+
+
+def ar1_image(h: int, w: int, rho: float = 0.95, sigma: float = 40.0,
+              mean: float = 128.0, seed: int = 0) -> np.ndarray:
+    """uint8 image: clip(round(mean + sigma*field), 0, 255)."""
+    rng = rng_for(seed)
+    y = ar1_field(h, w, rho, rng)
+    img = np.clip(_round_half_away(mean + sigma * y), 0, 255)
+    return img.astype(np.uint8)
+
+
+def ar1_batch_image(i: int, h: int, w: int, seed_base: int = 1000,
+                    rho_lo: float = 0.85, rho_hi: float = 0.98,
+                    sigma: float = 40.0, mean: float = 128.0):
+    """Image ``i`` of a batch whose per-image rho ~ U[rho_lo, rho_hi].
+
+    Both rho and the content come from seed ``seed_base + i``.  Returns
+    ``(image_uint8, rho)``.
+    """
+    rng = rng_for(seed_base + i)
+    rho = float(rng.uniform(rho_lo, rho_hi))
+    y = ar1_field(h, w, rho, rng)
+    img = np.clip(_round_half_away(mean + sigma * y), 0, 255).astype(np.uint8)
+    return img, rho
+
+
+def laplace_residual(h: int, w: int, scale: float = 12.0, clip: int = 255,
+                     seed: int = 0) -> np.ndarray:
+    """int16 i.i.d. Laplacian residual, rounded and clipped to [-clip, clip]."""
+    rng = rng_for(seed)
+    x = _round_half_away(rng.laplace(0.0, scale, size=(h, w)))
+    return np.clip(x, -clip, clip).astype(np.int16)
+
+
+def residual_frame_planes(frame: int, luma_h: int = 2160, luma_w: int = 3840,
+                          scale: float = 12.0, seed_base: int = 2000):
+    """One 4:2:0 residual frame: (Y, Cb, Cr) int16 planes.
+
+    Plane p of frame f uses seed ``seed_base + 3*f + p``.
+    """
+    planes = []
+    for p, (h, w) in enumerate([(luma_h, luma_w), (luma_h // 2, luma_w // 2),
+                                (luma_h // 2, luma_w // 2)]):
+        planes.append(laplace_residual(h, w, scale, 255, seed_base + 3 * frame + p))
+    return planes
+
+
+def quadtree_tus(h: int, w: int, rng: np.random.Generator, p_split: float = 0.4,
+                 ctu: int = 32, min_tu: int = 8) -> np.ndarray:
+    """HEVC-style quadtree partition of an h x w image into square TUs.
+
+    The image is covered by ctu x ctu coding-tree units.  Each unit splits into
+    four children with probability ``p_split`` per level down to ``min_tu``;
+    a unit that crosses the image border is always split (implicit split).
+    ``h`` and ``w`` must be multiples of ``min_tu``.
+
+    Returns an int32 array of rows ``(x, y, size)`` in raster CTU order.
+    """
+    assert h % min_tu == 0 and w % min_tu == 0
+    out = []
+
+    def visit(x, y, s):
+        if x >= w or y >= h:
+            return
+        inside = (x + s <= w) and (y + s <= h)
+        if s > min_tu and (not inside or rng.random() < p_split):
+            hs = s // 2
+            visit(x, y, hs)
+            visit(x + hs, y, hs)
+            visit(x, y + hs, hs)
+            visit(x + hs, y + hs, hs)
+        else:
+            out.append((x, y, s))
+
+    for cy in range(0, h, ctu):
+        for cx in range(0, w, ctu):
+            visit(cx, cy, ctu)
+    return np.asarray(out, dtype=np.int32).reshape(-1, 3)
+
+
+def ragged_sizes(n: int, seed: int, median: float = 512.0, sigma: float = 0.75,
+                 lo: int = 64, hi: int = 4096, mult: int = 8) -> np.ndarray:
+    """``n`` (height, width) pairs, each side log-normal in [lo, hi], floored
+    to a multiple of ``mult``."""
+    rng = rng_for(seed)
+    out = np.empty((n, 2), dtype=np.int64)
+    for i in range(n):
+        for j in range(2):
+            while True:
+                v = rng.lognormal(np.log(median), sigma)
+                if lo <= v <= hi:
+                    break
+            out[i, j] = int(v) // mult * mult
+    return out
+
+
+def poisson_arrivals(n: int, rate_hz: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds, float64) of a Poisson process."""
+    rng = rng_for(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
+
+
+def serving_requests(n: int, seed: int = 4000, rate_hz: float = 2000.0,
+                     median: float = 1024.0, sigma: float = 0.5,
+                     lo: int = 64, hi: int = 4096):
+    """Request trace for the serving loop.
+
+    Returns a list of dicts with keys ``t`` (arrival, s), ``h``, ``w``,
+    ``transform`` (1 or 2), ``n`` (8/16/32), ``r`` (6..28) and ``seed``
+    (content seed).  Sides are multiples of 32 so that every N fits.
+    """
+    rng = rng_for(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
+    reqs = []
+    for i in range(n):
+        hw = []
+        for _ in range(2):
+            while True:
+                v = rng.lognormal(np.log(median), sigma)
+                if lo <= v <= hi:
+                    break
+            hw.append(max(32, int(v) // 32 * 32))
+        reqs.append(dict(t=float(t[i]), h=hw[0], w=hw[1],
+                         transform=int(rng.integers(1, 3)),
+                         n=int((8, 16, 32)[rng.integers(0, 3)]),
+                         r=int(rng.integers(6, 29)),
+                         seed=int(seed * 100000 + i)))
+    return reqs
