@@ -1,0 +1,176 @@
+"""Block-wise Chen-based approximate DCT on MI355X (gfx950).
+
+Python front end of ``libadct.so``: it checks tensor placement and shapes,
+allocates outputs with PyTorch and passes raw device pointers and the current
+HIP stream to the C ABI declared in ``include/adct.h``.  Every step of the
+transform runs in the library's HIP kernels; there is no CPU path.
+
+Transforms (section 3 and section 6.1 of the paper):
+  T1 = the sign-based approximation T~_N (eq. 4 for N = 8),
+  T2 = the round-based approximation T^_N (eq. 5 for N = 8),
+  N in {8, 16, 32}; N = 16, 32 use the Chen-JAM recursion.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import ADCT_I16, ADCT_T1, ADCT_T2, ADCT_U8, AdctError
+
+__all__ = ["ADCT_T1", "ADCT_T2", "AdctError", "get_matrix", "zigzag", "scale_vector",
+           "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path"]
+
+library_path = _lib.LIB_PATH
+
+
+# ----------------------------------------------------------------- host queries
+def get_matrix(transform: int, n: int, inverse: bool = False) -> np.ndarray:
+    """T_N (or U_N = N T_N^-1) as computed by the library's butterflies."""
+    out = np.zeros((n, n), dtype=np.int32)
+    _lib.check(_lib.load().adct_get_matrix(transform, n, int(inverse), out.ctypes.data))
+    return out
+
+
+def zigzag(n: int) -> np.ndarray:
+    out = np.zeros(n * n, dtype=np.int32)
+    _lib.check(_lib.load().adct_zigzag(n, out.ctypes.data))
+    return out
+
+
+def scale_vector(transform: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    _lib.check(_lib.load().adct_scale_vector(transform, n, out.ctypes.data))
+    return out
+
+
+def quant_tables(transform: int, n: int, qstep: int):
+    mq = np.zeros((n, n), dtype=np.int32)
+    dq = np.zeros((n, n), dtype=np.int32)
+    _lib.check(_lib.load().adct_quant_tables(transform, n, qstep, mq.ctypes.data,
+                                             dq.ctypes.data))
+    return mq, dq
+
+
+# ----------------------------------------------------------------- device calls
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.uint8:
+        return ADCT_U8
+    if t.dtype == torch.int16:
+        return ADCT_I16
+    raise TypeError(f"pixels must be uint8 or int16, got {t.dtype}")
+
+
+def _image_geometry(x):
+    """(batch, height, width, pitch, image_stride) of a [B,H,W] or [H,W] tensor."""
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dim() != 3:
+        raise ValueError("images must be [H, W] or [B, H, W]")
+    if x.stride(2) != 1:
+        raise ValueError("image rows must be contiguous")
+    b, h, w = x.shape
+    return b, h, w, x.stride(1), (x.stride(0) if b > 1 else x.stride(1) * h)
+
+
+def _require_device(*tensors):
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libadct runs on the GPU only: pass device tensors")
+
+
+def _stream_handle(device) -> C.c_void_p:
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def fwd2d(x, transform: int, n: int, out=None):
+    """All coefficients of every tile: int32 [B, H/n, W/n, n, n]."""
+    torch = _torch()
+    _require_device(x, out)
+    b, h, w, pitch, istride = _image_geometry(x)
+    if out is None:
+        out = torch.empty((b, h // n, w // n, n, n), dtype=torch.int32, device=x.device)
+    _lib.check(_lib.load().adct_fwd2d(transform, n, _ptr(x), _dtype_code(x), b, h, w, pitch,
+                                      istride, _ptr(out), _stream_handle(x.device)))
+    return out
+
+
+def inv2d(coef, transform: int, n: int, r: int, qstep: int = 0, dtype=None, out=None):
+    """Reconstruct images from natural-order coefficients [B, H/n, W/n, n, n]."""
+    torch = _torch()
+    _require_device(coef, out)
+    if coef.dtype != torch.int32 or not coef.is_contiguous() or coef.dim() != 5:
+        raise ValueError("coefficients must be a contiguous int32 [B, H/n, W/n, n, n] tensor")
+    b, th, tw = coef.shape[:3]
+    if out is None:
+        out = torch.empty((b, th * n, tw * n), dtype=dtype or torch.uint8, device=coef.device)
+    ob, h, w, pitch, istride = _image_geometry(out)
+    _lib.check(_lib.load().adct_inv2d(transform, n, r, qstep, _ptr(coef), _ptr(out),
+                                      _dtype_code(out), ob, h, w, pitch, istride,
+                                      _stream_handle(coef.device)))
+    return out
+
+
+def compress(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True, scaled=True,
+             recon=True, sse=True):
+    """The fused pipeline.  Each of kept/scaled/recon/sse may be True (allocate),
+    False (skip) or a preallocated tensor.  Returns a dict of the produced
+    tensors: kept int32 [B, H/n, W/n, r], scaled float32 [B, H/n, W/n, r],
+    recon like x, sse uint64 [B] (accumulated into when passed in)."""
+    torch = _torch()
+    _require_device(x)
+    b, h, w, pitch, istride = _image_geometry(x)
+    dev = x.device
+    tiles = (b, h // n, w // n)
+
+    def pick(v, make):
+        if v is True:
+            return make()
+        if v is False or v is None:
+            return None
+        _require_device(v)
+        return v
+
+    kept_t = pick(kept, lambda: torch.empty(tiles + (r,), dtype=torch.int32, device=dev))
+    scaled_t = pick(scaled, lambda: torch.empty(tiles + (r,), dtype=torch.float32, device=dev))
+    recon_t = pick(recon, lambda: torch.empty_strided(x.size(), x.stride(), dtype=x.dtype,
+                                                        device=dev))
+    sse_t = pick(sse, lambda: torch.zeros(b, dtype=torch.uint64, device=dev))
+    if recon_t is not None:
+        rb, rh, rw, rp, rs = _image_geometry(recon_t)
+        if (rb, rh, rw, rp, rs) != (b, h, w, pitch, istride):
+            raise ValueError("recon must have the geometry of x")
+    _lib.check(_lib.load().adct_compress(transform, n, r, qstep, _ptr(x), _dtype_code(x), b, h,
+                                         w, pitch, istride, _ptr(kept_t), _ptr(scaled_t),
+                                         _ptr(recon_t), _ptr(sse_t), _stream_handle(dev)))
+    return {"kept": kept_t, "scaled": scaled_t, "recon": recon_t, "sse": sse_t}
+
+
+def decompress(kept, transform: int, n: int, r: int, qstep: int = 0, dtype=None, out=None):
+    """Reconstruct from zig-zag-ordered retained coefficients [B, H/n, W/n, r]."""
+    torch = _torch()
+    _require_device(kept, out)
+    if kept.dtype != torch.int32 or not kept.is_contiguous() or kept.dim() != 4:
+        raise ValueError("kept must be a contiguous int32 [B, H/n, W/n, r] tensor")
+    b, th, tw, rr = kept.shape
+    if rr != r:
+        raise ValueError("kept.shape[-1] must equal r")
+    if out is None:
+        out = torch.empty((b, th * n, tw * n), dtype=dtype or torch.uint8, device=kept.device)
+    ob, h, w, pitch, istride = _image_geometry(out)
+    _lib.check(_lib.load().adct_decompress(transform, n, r, qstep, _ptr(kept), _ptr(out),
+                                           _dtype_code(out), ob, h, w, pitch, istride,
+                                           _stream_handle(kept.device)))
+    return out

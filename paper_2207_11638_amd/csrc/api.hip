@@ -1,0 +1,309 @@
+// C ABI: argument checks, constant tables and kernel dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/adct.h"
+#include "adct_internal.hpp"
+
+namespace adct {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int ok() {
+  g_last_error.clear();
+  return ADCT_OK;
+}
+
+bool valid_kind(int t) { return t == ADCT_T1 || t == ADCT_T2; }
+bool valid_n(int n) { return n == 8 || n == 16 || n == 32; }
+
+// Apply the forward (inverse = false) or inverse butterfly of (kind, n) to a
+// vector on the host.
+void apply_1d(int kind, int n, bool inverse, int* v) {
+#define ADCT_APPLY(K, NN)                             \
+  do {                                                \
+    int tmp[NN];                                      \
+    for (int i = 0; i < NN; ++i) tmp[i] = v[i];       \
+    if (inverse) invN<K, NN>(tmp); else fwdN<K, NN>(tmp); \
+    for (int i = 0; i < NN; ++i) v[i] = tmp[i];       \
+  } while (0)
+  if (kind == KIND_SIGN) {
+    if (n == 8) ADCT_APPLY(KIND_SIGN, 8);
+    else if (n == 16) ADCT_APPLY(KIND_SIGN, 16);
+    else ADCT_APPLY(KIND_SIGN, 32);
+  } else {
+    if (n == 8) ADCT_APPLY(KIND_ROUND, 8);
+    else if (n == 16) ADCT_APPLY(KIND_ROUND, 16);
+    else ADCT_APPLY(KIND_ROUND, 32);
+  }
+#undef ADCT_APPLY
+}
+
+// Column j of the operator = operator applied to e_j.
+void operator_matrix(int kind, int n, bool inverse, std::vector<int>& m) {
+  m.assign(n * n, 0);
+  std::vector<int> e(n);
+  for (int j = 0; j < n; ++j) {
+    std::fill(e.begin(), e.end(), 0);
+    e[j] = 1;
+    apply_1d(kind, n, inverse, e.data());
+    for (int i = 0; i < n; ++i) m[i * n + j] = e[i];
+  }
+}
+
+// diag(T T^T) from the forward butterfly.
+void diag_ttt(int kind, int n, std::vector<int64_t>& d) {
+  std::vector<int> t;
+  operator_matrix(kind, n, false, t);
+  d.assign(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) d[i] += static_cast<int64_t>(t[i * n + j]) * t[i * n + j];
+}
+
+double round_half_away(double x) { return x < 0 ? -floor(-x + 0.5) : floor(x + 0.5); }
+
+struct TableSet {
+  Tables t;
+  std::vector<int32_t> mq_full, dq_full;
+};
+
+// Class tables: the distinct diagonal values (at most four) index the scale
+// and quantiser tables.
+int build_tables(int kind, int n, int qstep, TableSet& out) {
+  std::vector<int64_t> d;
+  diag_ttt(kind, n, d);
+  std::vector<int64_t> vals(d);
+  std::sort(vals.begin(), vals.end());
+  vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+  if (vals.size() > 4) return fail(ADCT_E_ARG, "internal: more than four row classes");
+  memset(&out.t, 0, sizeof(out.t));
+  for (int v = 0; v < n; ++v)
+    out.t.cls[v] = static_cast<uint8_t>(std::find(vals.begin(), vals.end(), d[v]) - vals.begin());
+  for (size_t a = 0; a < vals.size(); ++a)
+    for (size_t b = 0; b < vals.size(); ++b) {
+      const double dd = static_cast<double>(vals[a]) * static_cast<double>(vals[b]);
+      out.t.s2[a * 4 + b] = static_cast<float>(1.0 / sqrt(dd));
+      if (qstep > 0) {
+        const double g = qstep * sqrt(dd);
+        out.t.mq[a * 4 + b] = static_cast<int32_t>(round_half_away(16777216.0 / g));
+        out.t.dq[a * 4 + b] = static_cast<int32_t>(round_half_away(2.0 * g));
+      }
+    }
+  out.mq_full.assign(n * n, 0);
+  out.dq_full.assign(n * n, 0);
+  for (int v = 0; v < n; ++v)
+    for (int u = 0; u < n; ++u) {
+      const int ti = out.t.cls[v] * 4 + out.t.cls[u];
+      out.mq_full[v * n + u] = out.t.mq[ti];
+      out.dq_full[v * n + u] = out.t.dq[ti];
+    }
+  return ADCT_OK;
+}
+
+int pixel_bytes(int dtype) { return dtype == ADCT_U8 ? 1 : 2; }
+
+// Common checks of a pixel image set; fills g.
+int check_images(const char* what, int n, int dtype, const void* ptr, int batch, int height,
+                 int width, int64_t pitch, int64_t image_stride, Geom& g) {
+  if (dtype != ADCT_U8 && dtype != ADCT_I16) return fail(ADCT_E_ARG, "%s: bad dtype %d", what, dtype);
+  if (batch < 0 || height < 0 || width < 0)
+    return fail(ADCT_E_SHAPE, "%s: negative size", what);
+  if (height % n || width % n)
+    return fail(ADCT_E_SHAPE, "%s: %dx%d is not a multiple of n=%d", what, height, width, n);
+  if (pitch < width) return fail(ADCT_E_SHAPE, "%s: pitch %lld < width %d", what, (long long)pitch, width);
+  if (batch > 1 && image_stride < pitch * height)
+    return fail(ADCT_E_SHAPE, "%s: image_stride %lld < pitch*height", what, (long long)image_stride);
+  const int64_t align = std::min<int64_t>(16, static_cast<int64_t>(n) * pixel_bytes(dtype));
+  const int64_t bytes_pitch = pitch * pixel_bytes(dtype);
+  const int64_t bytes_stride = batch > 1 ? image_stride * pixel_bytes(dtype) : 0;
+  if (ptr != nullptr && ((reinterpret_cast<uintptr_t>(ptr) % align) || (bytes_pitch % align) ||
+                         (bytes_stride % align)))
+    return fail(ADCT_E_ALIGN, "%s: images and rows must be %lld-byte aligned", what, (long long)align);
+  g.pitch = pitch;
+  g.image_stride = image_stride;
+  g.batch = batch;
+  g.tiles_y = height / n;
+  g.tiles_x = width / n;
+  return ADCT_OK;
+}
+
+int check_common(int transform, int n) {
+  if (!valid_kind(transform)) return fail(ADCT_E_ARG, "bad transform id %d", transform);
+  if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d (8, 16 or 32)", n);
+  return ADCT_OK;
+}
+
+int check_r_q(int n, int r, int qstep) {
+  if (r < 1 || r > n * n) return fail(ADCT_E_ARG, "r=%d outside [1, %d]", r, n * n);
+  if (qstep < 0 || qstep > 4096) return fail(ADCT_E_ARG, "qstep=%d outside [0, 4096]", qstep);
+  return ADCT_OK;
+}
+
+int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stream_t stream) {
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int e = n == 8 ? launch_n8(mode, kind, dtype, p, s) : launch_jam(mode, kind, n, dtype, p, s);
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" {
+
+ADCT_API int adct_version(void) { return 1; }
+
+ADCT_API const char* adct_last_error(void) { return g_last_error.c_str(); }
+
+ADCT_API int adct_get_matrix(int transform, int n, int inverse, int32_t* host_out) {
+  if (int s = check_common(transform, n)) return s;
+  if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
+  std::vector<int> m;
+  operator_matrix(transform, n, inverse != 0, m);
+  for (int i = 0; i < n * n; ++i) {
+    if (inverse) {
+      // the inverse butterfly applies K_N = 2 U_N
+      if (m[i] % 2) return fail(ADCT_E_ARG, "internal: odd entry in the inverse chain");
+      host_out[i] = m[i] / 2;
+    } else {
+      host_out[i] = m[i];
+    }
+  }
+  return ok();
+}
+
+ADCT_API int adct_zigzag(int n, int32_t* host_out) {
+  if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d", n);
+  if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
+  for (int v = 0; v < n; ++v)
+    for (int u = 0; u < n; ++u) host_out[zz_pos(n, v, u)] = v * n + u;
+  return ok();
+}
+
+ADCT_API int adct_scale_vector(int transform, int n, double* host_out) {
+  if (int s = check_common(transform, n)) return s;
+  if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
+  std::vector<int64_t> d;
+  diag_ttt(transform, n, d);
+  for (int i = 0; i < n; ++i) host_out[i] = 1.0 / sqrt(static_cast<double>(d[i]));
+  return ok();
+}
+
+ADCT_API int adct_quant_tables(int transform, int n, int qstep, int32_t* mq, int32_t* dq) {
+  if (int s = check_common(transform, n)) return s;
+  if (qstep < 1 || qstep > 4096) return fail(ADCT_E_ARG, "qstep=%d outside [1, 4096]", qstep);
+  TableSet ts;
+  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  for (int i = 0; i < n * n; ++i) {
+    if (mq) mq[i] = ts.mq_full[i];
+    if (dq) dq[i] = ts.dq_full[i];
+  }
+  return ok();
+}
+
+ADCT_API int adct_fwd2d(int transform, int n, const void* d_src, int dtype, int batch, int height,
+                        int width, int64_t pitch, int64_t image_stride, int32_t* d_coef,
+                        adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  PassParams p{};
+  if (int s = check_images("fwd2d", n, dtype, d_src, batch, height, width, pitch, image_stride, p.g))
+    return s;
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  if (d_src == nullptr || d_coef == nullptr) return fail(ADCT_E_ARG, "fwd2d: null pointer");
+  if (reinterpret_cast<uintptr_t>(d_coef) % 16) return fail(ADCT_E_ALIGN, "fwd2d: d_coef must be 16-byte aligned");
+  p.src = d_src;
+  p.cout = d_coef;
+  p.r = n * n;
+  return launch(Mode::Forward, transform, n, dtype, p, stream);
+}
+
+static int inverse_common(Mode mode, int transform, int n, int r, int qstep, const int32_t* d_in,
+                          void* d_dst, int dtype, int batch, int height, int width, int64_t pitch,
+                          int64_t image_stride, adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  if (int s = check_r_q(n, r, qstep)) return s;
+  PassParams p{};
+  if (int s = check_images("inverse", n, dtype, d_dst, batch, height, width, pitch, image_stride, p.g))
+    return s;
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  if (d_in == nullptr || d_dst == nullptr) return fail(ADCT_E_ARG, "inverse: null pointer");
+  if (mode == Mode::Inverse && reinterpret_cast<uintptr_t>(d_in) % 16)
+    return fail(ADCT_E_ALIGN, "inv2d: d_coef must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(d_in) % 4) return fail(ADCT_E_ALIGN, "inverse: misaligned input");
+  TableSet ts;
+  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  p.t = ts.t;
+  p.cin = d_in;
+  p.dst = d_dst;
+  p.r = r;
+  p.qstep = qstep;
+  return launch(mode, transform, n, dtype, p, stream);
+}
+
+ADCT_API int adct_inv2d(int transform, int n, int r, int qstep, const int32_t* d_coef, void* d_dst,
+                        int dtype, int batch, int height, int width, int64_t pitch,
+                        int64_t image_stride, adct_stream_t stream) {
+  return inverse_common(Mode::Inverse, transform, n, r, qstep, d_coef, d_dst, dtype, batch, height,
+                        width, pitch, image_stride, stream);
+}
+
+ADCT_API int adct_decompress(int transform, int n, int r, int qstep, const int32_t* d_kept,
+                             void* d_dst, int dtype, int batch, int height, int width,
+                             int64_t pitch, int64_t image_stride, adct_stream_t stream) {
+  return inverse_common(Mode::Decompress, transform, n, r, qstep, d_kept, d_dst, dtype, batch,
+                        height, width, pitch, image_stride, stream);
+}
+
+ADCT_API int adct_compress(int transform, int n, int r, int qstep, const void* d_src, int dtype,
+                           int batch, int height, int width, int64_t pitch, int64_t image_stride,
+                           int32_t* d_kept, float* d_scaled, void* d_recon, uint64_t* d_sse,
+                           adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  if (int s = check_r_q(n, r, qstep)) return s;
+  PassParams p{};
+  if (int s = check_images("compress", n, dtype, d_src, batch, height, width, pitch, image_stride, p.g))
+    return s;
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  if (d_src == nullptr) return fail(ADCT_E_ARG, "compress: null source");
+  if (d_recon != nullptr && (reinterpret_cast<uintptr_t>(d_recon) %
+                             std::min<int64_t>(16, static_cast<int64_t>(n) * pixel_bytes(dtype))))
+    return fail(ADCT_E_ALIGN, "compress: misaligned reconstruction buffer");
+  if ((reinterpret_cast<uintptr_t>(d_kept) % 4) || (reinterpret_cast<uintptr_t>(d_scaled) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_sse) % 8))
+    return fail(ADCT_E_ALIGN, "compress: misaligned output buffer");
+  TableSet ts;
+  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  p.t = ts.t;
+  p.src = d_src;
+  p.dst = d_recon;
+  p.cout = d_kept;
+  p.scaled = d_scaled;
+  p.sse = reinterpret_cast<unsigned long long*>(d_sse);
+  p.r = r;
+  p.qstep = qstep;
+  return launch(Mode::Compress, transform, n, dtype, p, stream);
+}
+
+}  // extern "C"

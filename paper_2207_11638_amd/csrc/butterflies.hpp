@@ -1,0 +1,192 @@
+// Add-only fast algorithms of the Chen-based DCT approximations.
+//
+// Everything here is __host__ __device__ so that the library can build the
+// transform matrices it computes (for self-checks) with exactly the code the
+// kernels run.
+//
+// 8-point forward (sections 3, eqs. 4 and 5): x -> B8 -> M4 -> M3 -> M2 -> M1 -> P8.
+//   Kind 1 (T~8, sign of Chen's constants) costs 26 additions, kind 2 (T^8,
+//   round of the constants: alpha=1, beta=(1,1,1,0), gamma=(1,0)) costs 22.
+// 8-point inverse (eqs. 6 and 7): T^-1 = 1/2 B8^T M4^-1 M3^-1 M2^-1 M1^T P8^T.
+//   Each factor inverse is 1/2 times an integer matrix, so the code applies
+//   the integer chain K8 = B8 (2 M4^-1) (2 M3^-1) (2 M2^-1) M1^T P8^T = 16 T8^-1.
+// N-point (section 6.1): T_N = M_per diag(T_{N/2}, T_{N/2}) M_add, with
+//   M_add = [[I, Ibar], [Ibar, -I]] (N additions) and M_per the interleave
+//   (output 2k <- top half k, output 2k+1 <- bottom half k).  The inverse is
+//   T_N^-1 = 1/2 M_add^T diag(T_{N/2}^-1, T_{N/2}^-1) M_per^T; the integer chain
+//   K_N = M_add^T diag(K_{N/2}, K_{N/2}) M_per^T equals 2N T_N^-1.
+// So for every N the integer inverse chain K_N is twice U_N = N T_N^-1.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__) || defined(__HIP__)
+#include <hip/hip_runtime.h>
+#define ADCT_HD __host__ __device__ __forceinline__
+#else
+#define ADCT_HD inline
+#endif
+
+namespace adct {
+
+enum : int { KIND_SIGN = 1, KIND_ROUND = 2 };
+
+// ------------------------------------------------------------ 8-point forward
+template <int KIND>
+ADCT_HD void fwd8(int (&x)[8]) {
+  // B8: pre-additions
+  const int y0 = x[0] + x[7], y1 = x[1] + x[6], y2 = x[2] + x[5], y3 = x[3] + x[4];
+  const int y4 = x[3] - x[4], y5 = x[2] - x[5], y6 = x[1] - x[6], y7 = x[0] - x[7];
+  // M4 = diag(B4, A3(alpha = 1))
+  const int z0 = y0 + y3, z1 = y1 + y2, z2 = y1 - y2, z3 = y0 - y3;
+  const int z4 = y7, z5 = y5 + y6, z6 = y6 - y5, z7 = y4;
+  // M3 = diag(C~(alpha, gamma), A2)
+  const int w0 = z0 + z1, w1 = z0 - z1;
+  int w2, w3;
+  if constexpr (KIND == KIND_SIGN) {  // gamma = (1, 1)
+    w2 = z3 - z2;
+    w3 = z2 + z3;
+  } else {                            // gamma = (1, 0)
+    w2 = -z2;
+    w3 = z3;
+  }
+  const int w4 = z4 + z5, w5 = z4 - z5, w6 = z7 - z6, w7 = z6 + z7;
+  // M2 = diag(P4, A1(beta))
+  const int v0 = w0, v1 = w3, v2 = w1, v3 = w2;
+  int v4, v7;
+  if constexpr (KIND == KIND_SIGN) {  // beta = (1, 1, 1, 1)
+    v4 = w4 + w7;
+    v7 = w4 - w7;
+  } else {                            // beta = (1, 1, 1, 0)
+    v4 = w4;
+    v7 = -w7;
+  }
+  const int v5 = w5 + w6, v6 = w5 - w6;
+  // M1 = diag(I4, Ibar4 Q) followed by the output permutation P8
+  x[0] = v0;
+  x[1] = v4;
+  x[2] = v1;
+  x[3] = v6;
+  x[4] = v2;
+  x[5] = v5;
+  x[6] = v3;
+  x[7] = v7;
+}
+
+// ------------------------------------------------ 8-point inverse (K8 = 16 T^-1)
+template <int KIND>
+ADCT_HD void inv8(int (&X)[8]) {
+  // P8^T then M1^T
+  const int v0 = X[0], v1 = X[2], v2 = X[4], v3 = X[6];
+  const int v4 = X[1], v5 = X[5], v6 = X[3], v7 = X[7];
+  // 2 M2^-1 = diag(2 P4^T, 2 A1^-1)
+  const int w0 = 2 * v0, w1 = 2 * v2, w2 = 2 * v3, w3 = 2 * v1;
+  int w4, w7;
+  if constexpr (KIND == KIND_SIGN) {  // 2 A1^-1 = A1
+    w4 = v4 + v7;
+    w7 = v4 - v7;
+  } else {                            // 2 A1^-1 = diag(2, [[1,1],[1,-1]], -2)
+    w4 = 2 * v4;
+    w7 = -2 * v7;
+  }
+  const int w5 = v5 + v6, w6 = v5 - v6;
+  // 2 M3^-1
+  const int z0 = w0 + w1, z1 = w0 - w1;
+  int z2, z3;
+  if constexpr (KIND == KIND_SIGN) {
+    z2 = w3 - w2;
+    z3 = w2 + w3;
+  } else {
+    z2 = -2 * w2;
+    z3 = 2 * w3;
+  }
+  const int z4 = w4 + w5, z5 = w4 - w5, z6 = w7 - w6, z7 = w6 + w7;
+  // 2 M4^-1 = diag(B4, [[0,0,0,2],[0,1,-1,0],[0,1,1,0],[2,0,0,0]])
+  const int y0 = z0 + z3, y1 = z1 + z2, y2 = z1 - z2, y3 = z0 - z3;
+  const int y4 = 2 * z7, y5 = z5 - z6, y6 = z5 + z6, y7 = 2 * z4;
+  // B8 (B8^-1 = B8^T / 2 and B8^T = B8)
+  X[0] = y0 + y7;
+  X[1] = y1 + y6;
+  X[2] = y2 + y5;
+  X[3] = y3 + y4;
+  X[4] = y3 - y4;
+  X[5] = y2 - y5;
+  X[6] = y1 - y6;
+  X[7] = y0 - y7;
+}
+
+// ------------------------------------------------------ N-point (JAM) forward
+template <int KIND, int N>
+ADCT_HD void fwdN(int (&x)[N]) {
+  if constexpr (N == 8) {
+    fwd8<KIND>(x);
+  } else {
+    constexpr int H = N / 2;
+    int u[H], w[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      u[i] = x[i] + x[N - 1 - i];       // top half of M_add
+      w[i] = x[H - 1 - i] - x[H + i];   // bottom half of M_add
+    }
+    fwdN<KIND, H>(u);
+    fwdN<KIND, H>(w);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {       // M_per interleave
+      x[2 * k] = u[k];
+      x[2 * k + 1] = w[k];
+    }
+  }
+}
+
+// ------------------------------------------- N-point (JAM) inverse, K_N = 2N T^-1
+template <int KIND, int N>
+ADCT_HD void invN(int (&X)[N]) {
+  if constexpr (N == 8) {
+    inv8<KIND>(X);
+  } else {
+    constexpr int H = N / 2;
+    int p[H], q[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {       // M_per^T
+      p[k] = X[2 * k];
+      q[k] = X[2 * k + 1];
+    }
+    invN<KIND, H>(p);
+    invN<KIND, H>(q);
+#pragma unroll
+    for (int i = 0; i < H; ++i) {       // M_add^T = M_add
+      X[i] = p[i] + q[H - 1 - i];
+      X[H + i] = p[H - 1 - i] - q[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ zig-zag
+// Position of coefficient (v, u) (v vertical, u horizontal frequency) in the
+// JPEG zig-zag scan of an N x N block: anti-diagonals d = v + u in increasing
+// order, odd d scanned with increasing v, even d with decreasing v.
+ADCT_HD constexpr int zz_pos(int n, int v, int u) {
+  const int d = v + u;
+  if (d < n) {
+    const int base = d * (d + 1) / 2;
+    return base + ((d & 1) ? v : u);
+  }
+  const int tail = (2 * n - 1 - d) * (2 * n - d) / 2;
+  const int base = n * n - tail;
+  return base + ((d & 1) ? v - (d - n + 1) : (n - 1 - v));
+}
+
+// Rounded division by 2^S with the paper's round() (half away from zero):
+// round(z / 2^S) = (z + 2^(S-1) - [z < 0]) >> S  (arithmetic shift = floor).
+template <int S>
+ADCT_HD int round_shift(int z) {
+  return (z + (1 << (S - 1)) + (z >> 31)) >> S;
+}
+
+// Same, with a constant added to the quotient: round(z / 2^S) + OFF.
+template <int S, int OFF>
+ADCT_HD int round_shift_offset(int z) {
+  return (z + (1 << (S - 1)) + (OFF << S) + (z >> 31)) >> S;
+}
+
+}  // namespace adct

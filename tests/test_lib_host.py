@@ -1,0 +1,110 @@
+"""CPU checks of the HIP library: it loads, exports every declared entry point,
+its host-side queries agree with the oracle, and argument errors are reported
+before any GPU work (no compute calls here)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import matrices as M
+from oracle import pipeline as P
+import paper_2207_11638_amd as adct
+from paper_2207_11638_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.adct_version() >= 1
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", M.SIZES)
+def test_library_butterflies_compute_the_paper_matrices(kind, n):
+    # the forward butterfly applied to unit vectors reproduces T_N, and the
+    # inverse butterfly reproduces U_N = N T_N^-1
+    assert np.array_equal(adct.get_matrix(kind, n), M.transform_matrix(kind, n))
+    assert np.array_equal(adct.get_matrix(kind, n, inverse=True), M.scaled_inverse(kind, n))
+
+
+@pytest.mark.parametrize("n", M.SIZES)
+def test_zigzag_table(n):
+    want = [v * n + u for v, u in M.zigzag(n)]
+    assert adct.zigzag(n).tolist() == want
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", M.SIZES)
+def test_scale_vector(kind, n):
+    assert np.array_equal(adct.scale_vector(kind, n), M.scale_vector(kind, n))
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", M.SIZES)
+@pytest.mark.parametrize("qstep", (1, 8, 13, 16, 32, 64, 100, 4096))
+def test_quant_tables(kind, n, qstep):
+    mq, dq = adct.quant_tables(kind, n, qstep)
+    omq, odq = P.quant_tables(kind, n, qstep)
+    assert np.array_equal(mq, omq)
+    assert np.array_equal(dq, odq)
+
+
+def _compress(lib, **kw):
+    args = dict(transform=1, n=8, r=10, qstep=0, src=C.c_void_p(4096), dtype=0, batch=1,
+                height=64, width=64, pitch=64, stride=64 * 64, kept=None, scaled=None,
+                recon=None, sse=None, stream=None)
+    args.update(kw)
+    return lib.adct_compress(args["transform"], args["n"], args["r"], args["qstep"], args["src"],
+                             args["dtype"], args["batch"], args["height"], args["width"],
+                             args["pitch"], args["stride"], args["kept"], args["scaled"],
+                             args["recon"], args["sse"], args["stream"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(transform=3), -1), (dict(transform=0), -1), (dict(n=4), -1), (dict(n=64), -1),
+    (dict(r=0), -1), (dict(r=65), -1), (dict(n=16, r=257), -1), (dict(qstep=-1), -1),
+    (dict(qstep=4097), -1), (dict(dtype=2), -1), (dict(src=None), -1),
+    (dict(height=60), -2), (dict(width=20, pitch=20), -2), (dict(pitch=32), -2),
+    (dict(batch=2, stride=100), -2), (dict(batch=-1), -2),
+    (dict(src=C.c_void_p(4097)), -3), (dict(pitch=68), -3), (dict(n=16, pitch=72), -3),
+    (dict(dtype=1, pitch=68), -3), (dict(sse=C.c_void_p(4100)), -3),
+])
+def test_argument_errors_are_reported_before_launch(lib, kw, status):
+    assert _compress(lib, **kw) == status
+    assert lib.adct_last_error()
+
+
+def test_empty_image_sets_are_a_no_op(lib):
+    # empty tensors carry null pointers; nothing is launched
+    assert _compress(lib, batch=0, src=None) == 0
+    assert _compress(lib, height=0, src=None) == 0
+    assert lib.adct_fwd2d(1, 16, None, 0, 0, 16, 16, 16, 256, None, None) == 0
+    assert lib.adct_decompress(2, 8, 5, 0, None, None, 1, 1, 0, 8, 8, 0, None) == 0
+
+
+def test_other_entry_points_validate(lib):
+    p = C.c_void_p(4096)
+    assert lib.adct_fwd2d(1, 8, None, 0, 1, 8, 8, 8, 64, p, None) == -1
+    assert lib.adct_fwd2d(1, 8, p, 0, 1, 8, 8, 8, 64, C.c_void_p(4100), None) == -3
+    assert lib.adct_inv2d(1, 8, 0, 0, p, p, 0, 1, 8, 8, 8, 64, None) == -1
+    assert lib.adct_inv2d(2, 16, 10, 0, p, p, 0, 1, 24, 16, 16, 384, None) == -2
+    assert lib.adct_decompress(1, 32, 10, 0, None, p, 0, 1, 32, 32, 32, 1024, None) == -1
+    assert lib.adct_get_matrix(1, 12, 0, p) == -1
+    assert lib.adct_zigzag(7, p) == -1
+    assert lib.adct_quant_tables(1, 8, 0, p, p) == -1
+
+
+def test_python_front_end_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    x = torch.zeros((8, 8), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        adct.compress(x, 1, 8, 10)
+    with pytest.raises(ValueError):
+        adct.fwd2d(x, 1, 8)

@@ -259,3 +259,14 @@ def test_zigzag_is_a_permutation_by_antidiagonals(n):
     for (v0, u0), (v1, u1) in zip(zz, zz[1:]):
         if v0 + u0 == v1 + u1:
             assert abs(v1 - v0) == 1 and abs(u1 - u0) == 1
+
+
+@pytest.mark.parametrize("n", (8, 16, 32))
+def test_zigzag_prefix_keeps_a_prefix_of_every_column(n):
+    # for every r, the rows kept in column u by the first r scan positions are
+    # 0 .. c_u - 1 (the JAM kernels mask each column by such a count)
+    pos = {vu: k for k, vu in enumerate(M.zigzag(n))}
+    for r in range(n * n + 1):
+        for u in range(n):
+            kept = [v for v in range(n) if pos[(v, u)] < r]
+            assert kept == list(range(len(kept)))
