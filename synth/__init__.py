@@ -27,6 +27,7 @@ __all__ = [
     "ar1_field",
     "ar1_image",
     "ar1_batch_image",
+    "ar1_batch",
     "laplace_residual",
     "residual_frame_planes",
     "quadtree_tus",
@@ -45,26 +46,34 @@ def _round_half_away(x: np.ndarray) -> np.ndarray:
     return np.sign(x) * np.floor(np.abs(x) + 0.5)
 
 
-def _ar1_filter(w: np.ndarray, rho: float, axis: int) -> np.ndarray:
-    """Stationary unit-variance AR(1) recursion along ``axis``.
+def _ar1_along_rows(w: np.ndarray, rho: float) -> np.ndarray:
+    """Stationary unit-variance AR(1) recursion along each row (axis 1).
 
     y[0] = w[0];  y[n] = rho*y[n-1] + sqrt(1-rho^2)*w[n].
     """
     c = np.sqrt(1.0 - rho * rho)
     w = np.array(w, dtype=np.float64, copy=True)
-    idx = [slice(None)] * w.ndim
-    idx[axis] = 0
     # scale the first sample so that the filter output starts at y[0] = w[0]
-    w[tuple(idx)] /= c
-    return lfilter([c], [1.0, -rho], w, axis=axis)
+    w[:, 0] /= c
+    return lfilter([c], [1.0, -rho], w, axis=1)
+
+
+def _ar1_along_columns(w: np.ndarray, rho: float) -> np.ndarray:
+    """The same recursion down the columns (axis 0), one image row at a time."""
+    c = np.sqrt(1.0 - rho * rho)
+    y = np.empty_like(w)
+    y[0] = w[0]
+    for n in range(1, w.shape[0]):
+        np.multiply(y[n - 1], rho, out=y[n])
+        y[n] += c * w[n]
+    return y
 
 
 def ar1_field(h: int, w: int, rho: float, rng: np.random.Generator) -> np.ndarray:
     """Unit-variance 2D separable AR(1) Gaussian field (float64, h x w)."""
     white = rng.standard_normal((h, w))
-    y = _ar1_filter(white, rho, axis=1)
-    y = _ar1_filter(y, rho, axis=0)
-    return y
+    y = _ar1_along_rows(white, rho)
+    return _ar1_along_columns(y, rho)
 
 
 def ar1_image(h: int, w: int, rho: float = 0.95, sigma: float = 40.0,
@@ -89,6 +98,53 @@ def ar1_batch_image(i: int, h: int, w: int, seed_base: int = 1000,
     y = ar1_field(h, w, rho, rng)
     img = np.clip(_round_half_away(mean + sigma * y), 0, 255).astype(np.uint8)
     return img, rho
+
+
+def _fill_ar1(args):
+    name, shape, lo, hi, kw = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        out = np.ndarray(shape, dtype=np.uint8, buffer=shm.buf)
+        rhos = []
+        for i in range(lo, hi):
+            out[i], rho = ar1_batch_image(i, shape[1], shape[2], **kw)
+            rhos.append(rho)
+        del out
+        return lo, rhos
+    finally:
+        shm.close()
+
+
+def ar1_batch(n: int, h: int, w: int, workers: int = 1, **kw):
+    """Images 0..n-1 of ``ar1_batch_image`` as one (n, h, w) uint8 array.
+
+    With ``workers`` > 1 the images are drawn in worker processes into shared
+    memory; the content does not depend on the worker count.  Returns
+    ``(images, rhos)``.
+    """
+    if workers <= 1 or n < 2:
+        imgs = np.empty((n, h, w), dtype=np.uint8)
+        rhos = []
+        for i in range(n):
+            imgs[i], rho = ar1_batch_image(i, h, w, **kw)
+            rhos.append(rho)
+        return imgs, np.array(rhos)
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=n * h * w)
+    try:
+        chunk = max(1, n // (workers * 4))
+        jobs = [(shm.name, (n, h, w), lo, min(n, lo + chunk), kw) for lo in range(0, n, chunk)]
+        rhos = np.zeros(n)
+        with mp.get_context("fork").Pool(workers) as pool:
+            for lo, rr in pool.imap_unordered(_fill_ar1, jobs):
+                rhos[lo:lo + len(rr)] = rr
+        imgs = np.ndarray((n, h, w), dtype=np.uint8, buffer=shm.buf).copy()
+        return imgs, rhos
+    finally:
+        shm.close()
+        shm.unlink()
 
 
 def laplace_residual(h: int, w: int, scale: float = 12.0, clip: int = 255,
