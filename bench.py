@@ -63,6 +63,61 @@ def measured_traffic():
     return t.get("hbm_bytes_per_launch_avg")
 
 
+COPY_BYTES = 1 << 30
+
+
+def _read_pmc(d, counter):
+    """{kernel name: [value per dispatch]} from a rocprofv3 --pmc csv run."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """Counters are KiB per dispatch; each is scaled by what it reads for a plain
+    copy kernel of COPY_BYTES (read COPY_BYTES, write COPY_BYTES)."""
+    fetch = _read_pmc(fetch_dir, "FETCH_SIZE")
+    write = _read_pmc(write_dir, "WRITE_SIZE")
+
+    def pick(d, pred):
+        vals = [v for k, vs in d.items() if pred(k) for v in vs]
+        return vals
+
+    is_copy = lambda k: "elementwise" in k and "add" in k.lower() or "CUDAFunctor_add" in k
+    is_fused = lambda k: "compress8<" in k
+    cf, cw = pick(fetch, is_copy), pick(write, is_copy)
+    if not cf or not cw:
+        raise SystemExit("calibration copy kernel not found in the counter runs")
+    fscale = COPY_BYTES / (cf[0] * 1024.0)
+    wscale = COPY_BYTES / (cw[0] * 1024.0)
+    per = {}
+    for name in set(fetch) | set(write):
+        if not is_fused(name):
+            continue
+        f = fetch.get(name, [0.0])
+        w = write.get(name, [0.0])
+        fb = sum(f) / len(f) * 1024.0 * fscale
+        wb = sum(w) / len(w) * 1024.0 * wscale
+        per[name] = {"fetch_bytes": fb, "write_bytes": wb}
+    if not per:
+        raise SystemExit("no fused kernel dispatches in the counter runs")
+    avg = sum(v["fetch_bytes"] + v["write_bytes"] for v in per.values()) / len(per)
+    out = {"source_digest": kernel_source_digest(), "copy_bytes": COPY_BYTES,
+           "fetch_scale": fscale, "write_scale": wscale,
+           "hbm_bytes_per_launch_avg": avg, "kernels": per}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps({"hbm_bytes_per_launch_avg": avg, "fetch_scale": fscale,
+                      "write_scale": wscale}))
+
+
 # ------------------------------------------------------------------ CPU leg
 def _oracle_task(args):
     img_seed, kind, r, h, w = args
@@ -74,7 +129,7 @@ def _oracle_task(args):
     return time.perf_counter() - t0, img.size
 
 
-def cpu_baseline(h, w, images=4):
+def cpu_baseline(h, w, images=12):
     """The oracle as it stands, over a bounded sample: the full 14-point sweep
     on ``images`` images, one (image, T, r) task per worker process."""
     import multiprocessing as mp
@@ -102,7 +157,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy kernel first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "benchmark into the committed traffic summary, then exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -131,6 +194,14 @@ def main():
     sse = torch.zeros(b, dtype=torch.uint64, device=dev)
     torch.cuda.synchronize()
     log("inputs resident on the GPU")
+
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.add(src, 0, out=dst)   # one elementwise kernel: reads and writes COPY_BYTES
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy done")
 
     combos = [(k, r) for k in KINDS for r in SWEEP_R]
 

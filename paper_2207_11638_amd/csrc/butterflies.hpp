@@ -189,4 +189,16 @@ ADCT_HD int round_shift_offset(int z) {
   return (z + (1 << (S - 1)) + (OFF << S) + (z >> 31)) >> S;
 }
 
+// round(z / 2^S) + 128 clipped to [0, 255].  The clip is applied to the
+// dividend (floor(t / 2^S) clipped to [0, 255] equals floor(clip(t, 0,
+// 2^(S+8) - 1) / 2^S)), followed by a logical shift: this form keeps the
+// compiler from fusing shift, saturation and byte packing into one gfx950
+// instruction whose upper result bits it wrongly assumes to be zero.
+template <int S>
+ADCT_HD int round_shift_u8(int z) {
+  const int t = z + (1 << (S - 1)) + (128 << S) + (z >> 31);
+  const int c = t < 0 ? 0 : (t > (256 << S) - 1 ? (256 << S) - 1 : t);
+  return static_cast<int>(static_cast<unsigned>(c) >> S);
+}
+
 }  // namespace adct

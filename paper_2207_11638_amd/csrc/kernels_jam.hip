@@ -101,7 +101,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     if constexpr (DT == DT_U8)
-      y[j] = min(max(round_shift_offset<S, 128>(z[j]), 0), 255);
+      y[j] = round_shift_u8<S>(z[j]);
     else
       y[j] = min(max(round_shift<S>(z[j]), -32768), 32767);
   }
