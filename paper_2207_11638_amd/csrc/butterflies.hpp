@@ -201,4 +201,20 @@ ADCT_HD int round_shift_u8(int z) {
   return static_cast<int>(static_cast<unsigned>(c) >> S);
 }
 
+#if defined(__HIPCC__) || defined(__HIP__)
+// Streaming stores: every output word is written once and not read again by
+// the kernel, so the stores carry the non-temporal hint.
+__device__ __forceinline__ void st_stream(uint32_t* p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+  __builtin_nontemporal_store(v.z, &p->z);
+  __builtin_nontemporal_store(v.w, &p->w);
+}
+#endif
+
 }  // namespace adct

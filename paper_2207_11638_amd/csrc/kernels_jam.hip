@@ -134,7 +134,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
           const int* yy = y + 16 * q + 4 * d;
           ws[d] = yy[0] | (yy[1] << 8) | (yy[2] << 16) | (yy[3] << 24);
         }
-        p[q] = make_uint4(ws[0], ws[1], ws[2], ws[3]);
+        st_stream(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
       }
     } else {
       uint4* p = reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off);
@@ -146,7 +146,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
           const int* yy = y + 8 * q + 2 * d;
           ws[d] = (yy[0] & 0xffff) | (static_cast<uint32_t>(yy[1]) << 16);
         }
-        p[q] = make_uint4(ws[0], ws[1], ws[2], ws[3]);
+        st_stream(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
       }
     }
   }
@@ -246,7 +246,8 @@ __device__ __forceinline__ void read_row(const int* S, int i, int k, int (&z)[N]
 // Copy ``count`` contiguous words from LDS to global memory (all threads).
 template <typename T>
 __device__ __forceinline__ void copy_out(T* dst, const int* src, int count) {
-  for (int e = threadIdx.x; e < count; e += kBlock) dst[e] = __builtin_bit_cast(T, src[e]);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int e = threadIdx.x; e < count; e += kBlock) st_stream(d + e, static_cast<uint32_t>(src[e]));
 }
 
 // ------------------------------------------------------------------ kernels

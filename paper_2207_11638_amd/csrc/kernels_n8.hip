@@ -121,11 +121,11 @@ __device__ __forceinline__ void store_raw(void* dst, int64_t off, int64_t pitch,
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
     if constexpr (DT == DT_U8)
-      *reinterpret_cast<uint2*>(static_cast<uint8_t*>(dst) + off + i * pitch) =
-          make_uint2(raw.w[i][0], raw.w[i][1]);
+      st_stream(reinterpret_cast<uint2*>(static_cast<uint8_t*>(dst) + off + i * pitch),
+                make_uint2(raw.w[i][0], raw.w[i][1]));
     else
-      *reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off + i * pitch) =
-          make_uint4(raw.w[i][0], raw.w[i][1], raw.w[i][2], raw.w[i][3]);
+      st_stream(reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off + i * pitch),
+                make_uint4(raw.w[i][0], raw.w[i][1], raw.w[i][2], raw.w[i][3]));
   }
 }
 
@@ -243,7 +243,12 @@ __device__ __forceinline__ void copy_tiles_out(uint32_t* g, const int* lds, int 
 #pragma unroll
   for (int t0 = 0; t0 < kWave; t0 += Q) {
     const int t = t0 + lt;
-    if (t < nact) g[t * R + kk] = static_cast<uint32_t>(lds[t * RS + kk]);
+    if (t < nact) {
+      // a pass stores Q*R consecutive words: the streaming hint pays only when
+      // that is a whole number of cache lines; otherwise L2 merges partial lines
+      if constexpr (Q * R == kWave) st_stream(g + t * R + kk, static_cast<uint32_t>(lds[t * RS + kk]));
+      else g[t * R + kk] = static_cast<uint32_t>(lds[t * RS + kk]);
+    }
   }
 }
 
@@ -374,7 +379,8 @@ __global__ __launch_bounds__(kWave) void forward8(PassParams p) {
     const int t = t0 + lt;
     if (t < w.nact) {
       const int* s = lds + t * RS + 4 * gq;
-      out[t * 16 + gq] = make_int4(s[0], s[1], s[2], s[3]);
+      st_stream(reinterpret_cast<uint4*>(out + t * 16 + gq),
+                make_uint4(s[0], s[1], s[2], s[3]));
     }
   }
 }
