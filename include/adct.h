@@ -146,6 +146,86 @@ ADCT_API int adct_decompress(int transform, int n, int r, int qstep, const int32
                              void* d_dst, int dtype, int batch, int height, int width,
                              int64_t pitch, int64_t image_stride, adct_stream_t stream);
 
+/* ----------------------------------------------------------------------
+ * Ragged batches: many images of different sizes, each partitioned into
+ * square transform units (TUs) of 8, 16 or 32 pixels (an HEVC-style quadtree;
+ * section 6 embeds the 16- and 32-point transforms in such a coder).
+ *
+ * A plan sorts the TUs into buckets of one size, transform and step (and, for
+ * 8x8 TUs, r <= 32 or not), orders each bucket by image and cuts it into work
+ * items of one image each, sized to one workgroup.  It owns that device work
+ * list until adct_batch_destroy.  adct_batch_run processes every TU with the
+ * fused pipeline of adct_compress: one launch per bucket over all images, a
+ * replay of that launch sequence captured in a HIP graph, or (for
+ * comparison) one launch per image and bucket.  A plan is not thread-safe;
+ * concurrent runs of one plan race on its graph cache.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t src_offset; /* pixel offset of the image's pixel (0, 0) in d_src      */
+  int64_t dst_offset; /* pixel offset of its reconstruction in d_dst            */
+  int32_t height;     /* pixels, multiple of 8                                  */
+  int32_t width;      /* pixels, multiple of 8                                  */
+  int32_t pitch;      /* pixels between rows (same in d_src and d_dst), >= width */
+  int32_t transform;  /* ADCT_T1 or ADCT_T2                                     */
+  int32_t r;          /* zig-zag prefix kept per TU (a TU of size n keeps min(r, n*n)) */
+  int32_t qstep;      /* 0 (zonal) or 1..4096 (quantiser, see adct_quant_tables) */
+} adct_image_desc_t;
+
+typedef struct {
+  int32_t image; /* index into the image table                  */
+  int32_t x;     /* left column of the TU, multiple of n          */
+  int32_t y;     /* top row of the TU, multiple of n              */
+  int32_t n;     /* 8, 16 or 32; the TU must lie inside the image */
+} adct_tu_desc_t;
+
+typedef struct adct_batch adct_batch_t;
+
+#define ADCT_RUN_BATCHED 0   /* one launch per bucket, covering every image      */
+#define ADCT_RUN_GRAPH 1     /* replay of that sequence captured in a HIP graph  */
+#define ADCT_RUN_PER_IMAGE 2 /* one launch per image and bucket (baseline)       */
+
+/* Build a plan (host arrays in, device work list out; allocates device memory
+ * and synchronises the device).  dtype is ADCT_U8 or ADCT_I16 for every
+ * image.  Image offsets and pitches must be multiples of 16 bytes.  The
+ * retained coefficients of all TUs are packed into one array of *kept_words
+ * words: TU t owns words [tu_kept_offset[t], + min(r, n*n)) in zig-zag order
+ * (tu_kept_offset may be NULL).  TUs may be given in any order; TUs of one
+ * image must not overlap. */
+ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
+                               const adct_tu_desc_t* tus, int64_t n_tus, int dtype,
+                               int64_t* tu_kept_offset, int64_t* kept_words,
+                               adct_batch_t** plan);
+
+ADCT_API int adct_batch_destroy(adct_batch_t* plan);
+
+/* Run the plan.  d_src/d_dst are pixel arenas addressed by the image
+ * descriptors (16-byte aligned); d_kept/d_scaled hold kept_words int32/float
+ * words; d_sse and d_psnr hold one uint64/float per image.  d_sse is
+ * overwritten with the error energy of this run and d_psnr receives
+ * 10 log10(255^2 H W / sse) (+inf when sse = 0) in single precision.  Any
+ * output may be NULL, except that d_psnr needs d_sse.  mode is one of
+ * ADCT_RUN_*; ADCT_RUN_GRAPH needs a non-null stream and re-captures only
+ * when a buffer or the stream changes. */
+ADCT_API int adct_batch_run(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
+                            float* d_scaled, uint64_t* d_sse, float* d_psnr, int mode,
+                            adct_stream_t stream);
+
+/* Workgroup sizes: bs8 threads (64 or 256) for 8x8 buckets, bs_jam (128 or
+ * 256) for 16x16 and 32x32 buckets; a workgroup processes bs8 8x8 TUs or
+ * bs_jam / n larger TUs.  adct_batch_tune times both candidates of every
+ * bucket on the given buffers (synchronising the stream), keeps the fastest
+ * and writes it to chosen[bucket] (chosen may be NULL); when the environment
+ * variable ADCT_TUNE_CACHE names a file, choices are cached there keyed by
+ * device architecture and bucket shape and reused by later plans. */
+ADCT_API int adct_batch_set_shape(adct_batch_t* plan, int bs8, int bs_jam);
+ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
+                             float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen);
+
+/* Work-list statistics: out[0..7] = images, TUs, work items, items of size
+ * 8, 16 and 32, buckets, compute units of the device. */
+ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,8 @@ from . import _lib
 from ._lib import ADCT_I16, ADCT_T1, ADCT_T2, ADCT_U8, AdctError
 
 __all__ = ["ADCT_T1", "ADCT_T2", "AdctError", "get_matrix", "zigzag", "scale_vector",
-           "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path"]
+           "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path",
+           "BatchPlan", "IMAGE_DESC", "TU_DESC"]
 
 library_path = _lib.LIB_PATH
 
@@ -174,3 +175,76 @@ def decompress(kept, transform: int, n: int, r: int, qstep: int = 0, dtype=None,
                                            _dtype_code(out), ob, h, w, pitch, istride,
                                            _stream_handle(kept.device)))
     return out
+
+
+# ----------------------------------------------------------------- ragged batches
+# numpy mirrors of adct_image_desc_t and adct_tu_desc_t
+IMAGE_DESC = np.dtype([("src_offset", np.int64), ("dst_offset", np.int64), ("height", np.int32),
+                       ("width", np.int32), ("pitch", np.int32), ("transform", np.int32),
+                       ("r", np.int32), ("qstep", np.int32)])
+TU_DESC = np.dtype([("image", np.int32), ("x", np.int32), ("y", np.int32), ("n", np.int32)])
+
+_RUN_MODES = {"batched": _lib.ADCT_RUN_BATCHED, "graph": _lib.ADCT_RUN_GRAPH,
+              "per_image": _lib.ADCT_RUN_PER_IMAGE}
+
+
+class BatchPlan:
+    """A plan for many images, each split into 8/16/32 transform units.
+
+    images: structured array of IMAGE_DESC (offsets in pixels into the source
+    and reconstruction arenas); tus: structured array of TU_DESC; dtype:
+    torch.uint8 or torch.int16.  After construction ``kept_words`` is the
+    length of the retained-coefficient arena and ``tu_kept_offset[t]`` the
+    first word of TU t in it."""
+
+    def __init__(self, images, tus, dtype):
+        torch = _torch()
+        self.images = np.ascontiguousarray(images, dtype=IMAGE_DESC)
+        self.tus = np.ascontiguousarray(tus, dtype=TU_DESC)
+        code = ADCT_U8 if dtype == torch.uint8 else ADCT_I16
+        self.dtype = dtype
+        self.tu_kept_offset = np.zeros(len(self.tus), dtype=np.int64)
+        words = C.c_int64(0)
+        handle = C.c_void_p()
+        _lib.check(_lib.load().adct_batch_create(
+            self.images.ctypes.data, len(self.images), self.tus.ctypes.data, len(self.tus), code,
+            self.tu_kept_offset.ctypes.data, C.byref(words), C.byref(handle)))
+        self._h = handle
+        self.kept_words = int(words.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().adct_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _lib.check(_lib.load().adct_batch_info(self._h, out.ctypes.data))
+        keys = ("images", "tus", "items", "items8", "items16", "items32", "buckets", "cus")
+        return dict(zip(keys, out.tolist()))
+
+    def set_shape(self, bs8: int, bs_jam: int):
+        _lib.check(_lib.load().adct_batch_set_shape(self._h, bs8, bs_jam))
+
+    def tune(self, src, dst=None, kept=None, scaled=None, sse=None):
+        _require_device(src, dst, kept, scaled, sse)
+        chosen = np.zeros(max(1, self.info()["buckets"]), dtype=np.int32)
+        _lib.check(_lib.load().adct_batch_tune(self._h, _ptr(src), _ptr(dst), _ptr(kept),
+                                               _ptr(scaled), _ptr(sse),
+                                               _stream_handle(src.device), chosen.ctypes.data))
+        return chosen
+
+    def run(self, src, dst=None, kept=None, scaled=None, sse=None, psnr=None, mode="batched"):
+        """Enqueue one pass over every TU on the current stream.  Buffers are
+        device tensors (or None): src/dst pixel arenas, kept int32 / scaled
+        float32 of kept_words words, sse uint64 / psnr float32 per image."""
+        _require_device(src, dst, kept, scaled, sse, psnr)
+        _lib.check(_lib.load().adct_batch_run(self._h, _ptr(src), _ptr(dst), _ptr(kept),
+                                              _ptr(scaled), _ptr(sse), _ptr(psnr),
+                                              _RUN_MODES[mode], _stream_handle(src.device)))

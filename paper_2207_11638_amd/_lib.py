@@ -29,7 +29,15 @@ _SIGNATURES = {
                          _vp], _i32),
     "adct_compress": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp,
                        _vp, _vp, _vp], _i32),
+    "adct_batch_create": ([_vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp], _i32),
+    "adct_batch_destroy": ([_vp], _i32),
+    "adct_batch_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
+    "adct_batch_set_shape": ([_vp, _i32, _i32], _i32),
+    "adct_batch_tune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "adct_batch_info": ([_vp, _vp], _i32),
 }
+
+ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE = 0, 1, 2
 
 _lib = None
 

@@ -87,16 +87,28 @@ struct TableSet {
 
 // Class tables: the distinct diagonal values (at most four) index the scale
 // and quantiser tables.
+template <int KIND, int N>
+void classes_of(std::vector<int64_t>& vals, std::vector<int>& cls) {
+  const RowClasses<N> rc = row_classes<KIND, N>();   // the kernels use the same numbering
+  vals.assign(rc.value, rc.value + rc.count);
+  cls.assign(rc.cls, rc.cls + N);
+}
+
 int build_tables(int kind, int n, int qstep, TableSet& out) {
-  std::vector<int64_t> d;
-  diag_ttt(kind, n, d);
-  std::vector<int64_t> vals(d);
-  std::sort(vals.begin(), vals.end());
-  vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+  std::vector<int64_t> vals;
+  std::vector<int> cls;
+  if (kind == KIND_SIGN) {
+    if (n == 8) classes_of<KIND_SIGN, 8>(vals, cls);
+    else if (n == 16) classes_of<KIND_SIGN, 16>(vals, cls);
+    else classes_of<KIND_SIGN, 32>(vals, cls);
+  } else {
+    if (n == 8) classes_of<KIND_ROUND, 8>(vals, cls);
+    else if (n == 16) classes_of<KIND_ROUND, 16>(vals, cls);
+    else classes_of<KIND_ROUND, 32>(vals, cls);
+  }
   if (vals.size() > 4) return fail(ADCT_E_ARG, "internal: more than four row classes");
   memset(&out.t, 0, sizeof(out.t));
-  for (int v = 0; v < n; ++v)
-    out.t.cls[v] = static_cast<uint8_t>(std::find(vals.begin(), vals.end(), d[v]) - vals.begin());
+  for (int v = 0; v < n; ++v) out.t.cls[v] = static_cast<uint8_t>(cls[v]);
   for (size_t a = 0; a < vals.size(); ++a)
     for (size_t b = 0; b < vals.size(); ++b) {
       const double dd = static_cast<double>(vals[a]) * static_cast<double>(vals[b]);
@@ -167,6 +179,20 @@ int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stre
 }
 
 }  // namespace
+
+int set_error(int status, const char* msg) {
+  if (status == ADCT_OK) g_last_error.clear();
+  else g_last_error = msg;
+  return status;
+}
+
+int build_tables_for(int kind, int n, int qstep, Tables* out) {
+  TableSet ts;
+  if (int s = build_tables(kind, n, qstep, ts)) return s;
+  *out = ts.t;
+  return ADCT_OK;
+}
+
 }  // namespace adct
 
 using namespace adct;

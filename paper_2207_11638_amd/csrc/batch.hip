@@ -1,0 +1,642 @@
+// Ragged batches: transform units (TUs) of mixed sizes from many images.
+//
+// Plan.  TUs are split into buckets by (size, transform, quantiser step, and
+// for 8x8 TUs whether r <= 32) and sorted by image inside each bucket.  A
+// bucket is processed by one launch of a kernel specialised for it, so each
+// kernel keeps the register footprint of the plain kernels and its constant
+// tables travel as kernel arguments.  A work item is a run of TUs of one image
+// sized to one workgroup pass: one 8x8 TU per thread, or one row/column per
+// thread for 16x16 and 32x32 TUs.  The retained coefficients of an item are
+// contiguous, so a group's outputs are written as one block.
+//
+// Run.  A run is: clear the per-image error energies, one launch per bucket
+// over all of its items (the hardware dispatcher balances the workgroups),
+// then the per-image PSNR.  The same sequence can be captured in a HIP graph
+// and replayed, or, as a baseline, issued as one launch per image and bucket.
+//
+// Shape.  The workgroup size of every bucket (8x8: 64 or 256 threads; 16x16
+// and 32x32: 128 or 256) is chosen by adct_batch_tune, which times the
+// candidates on the caller's buffers and caches the choice.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/adct.h"
+#include "jam_group.hpp"
+#include "tile8.hpp"
+
+namespace adct {
+
+// defined in api.hip
+int set_error(int status, const char* msg);
+int build_tables_for(int kind, int n, int qstep, Tables* out);
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kStagedRB = 32;  // 8x8 buckets with r <= 32 stage their outputs through LDS
+
+struct BImage {
+  int64_t src_off;   // pixels
+  int64_t dst_off;   // pixels
+  int64_t npix;      // height * width
+  int32_t pitch;
+  int32_t r;
+};
+
+struct BItem {
+  int32_t image;
+  int32_t tu_begin;  // index into the sorted position list
+  int32_t count;     // TUs in this item
+  int32_t pad;
+  int64_t kept_base; // word offset of the item's first retained coefficient
+};
+
+struct BucketParams {
+  const BImage* imgs;
+  const BItem* items;     // this bucket's items
+  const int2* pos;        // (x, y) of every TU, sorted
+  const void* src;
+  void* dst;
+  int32_t* kept;
+  float* scaled;
+  unsigned long long* sse;
+  int item_begin;         // first item of this launch
+  Tables t;
+};
+
+template <typename T>
+__device__ __forceinline__ T* offset_px(T* base, int64_t px, int esize) {
+  return base == nullptr ? nullptr
+                         : reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + px * esize);
+}
+
+// 8x8 TUs: BS / 64 waves, one TU per thread.
+template <int DT, int KIND, bool QUANT, bool STAGED, int BS>
+__global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
+  constexpr int RB = STAGED ? kStagedRB : 64;
+  constexpr int esize = DT == DT_U8 ? 1 : 2;
+  __shared__ int S[STAGED ? BS * t8::row_stride(kStagedRB) : 1];
+  const BItem it = p.items[p.item_begin + blockIdx.x];
+  const BImage im = p.imgs[it.image];
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  t8::WaveIO io;
+  io.src = offset_px(p.src, im.src_off, esize);
+  io.dst = offset_px(p.dst, im.dst_off, esize);
+  io.pitch = im.pitch;
+  io.lane = lane;
+  io.nact = min(kWave, max(0, it.count - w * kWave));
+  io.active = lane < io.nact;
+  int2 xy = make_int2(0, 0);
+  if (io.active) xy = p.pos[it.tu_begin + w * kWave + lane];
+  io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
+  const int r = min(im.r, 64);
+  io.r = r;
+  const int64_t kb = it.kept_base + static_cast<int64_t>(w) * kWave * r;
+  io.kept = p.kept != nullptr ? p.kept + kb : nullptr;
+  io.scaled = p.scaled != nullptr ? p.scaled + kb : nullptr;
+  io.sse = p.sse != nullptr ? p.sse + it.image : nullptr;
+  t8::compress_wave<KIND, DT, RB, QUANT, STAGED>(S + (STAGED ? w * kWave * t8::row_stride(RB) : 0),
+                                                 p.t, io);
+}
+
+// 16x16 / 32x32 TUs: BS / N tiles per workgroup.
+template <int DT, int KIND, int N, bool QUANT, int BS>
+__global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
+  constexpr int esize = DT == DT_U8 ? 1 : 2;
+  using C = jam::Cfg<N, BS>;
+  __shared__ int S[C::WORDS];
+  __shared__ jam::Shared sh;
+  jam::load_tables(sh, p.t, N);
+  const BItem it = p.items[p.item_begin + blockIdx.x];
+  const BImage im = p.imgs[it.image];
+  const int k = threadIdx.x % C::TPW;
+  jam::GroupIO io;
+  io.src = offset_px(p.src, im.src_off, esize);
+  io.dst = offset_px(p.dst, im.dst_off, esize);
+  io.pitch = im.pitch;
+  io.nact = it.count;
+  io.active = k < it.count;
+  int2 xy = make_int2(0, 0);
+  if (io.active) xy = p.pos[it.tu_begin + k];
+  io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
+  const int r = min(im.r, N * N);
+  io.r = r;
+  io.kept = p.kept != nullptr ? p.kept + it.kept_base : nullptr;
+  io.scaled = p.scaled != nullptr ? p.scaled + it.kept_base : nullptr;
+  io.sse = p.sse != nullptr ? p.sse + it.image : nullptr;
+  jam::compress_group<KIND, N, DT, QUANT, BS>(S, sh, io);
+}
+
+__global__ void zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void psnr_kernel(const unsigned long long* sse, const BImage* imgs, float* psnr, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long e = sse[i];
+  psnr[i] = e == 0ull ? INFINITY
+                      : 10.0f * log10f(65025.0f * static_cast<float>(imgs[i].npix) /
+                                       static_cast<float>(e));
+}
+
+// ------------------------------------------------------------- host side
+struct Bucket {
+  int log2n = 3;
+  int kind = 1;
+  int qstep = 0;
+  bool staged = true;    // 8x8 only
+  int bs = 256;          // threads per workgroup
+  Tables tables{};
+  int64_t tu_begin = 0;  // first TU in the sorted order
+  int64_t tu_end = 0;
+  std::vector<BItem> items;
+  std::vector<std::pair<int, int>> image_ranges;  // [begin, end) items of each image present
+  BItem* d_items = nullptr;
+  size_t d_cap = 0;
+};
+
+int tus_per_item(const Bucket& b) { return b.log2n == 3 ? b.bs : b.bs >> b.log2n; }
+
+template <int DT, int KIND>
+void launch_bucket_typed(const Bucket& b, BucketParams p, int first, int count, hipStream_t s) {
+  p.item_begin = first;
+  const dim3 grid(count);
+#define ADCT_B8(Q, ST, BS) bucket8<DT, KIND, Q, ST, BS><<<grid, BS, 0, s>>>(p)
+  if (b.log2n == 3) {
+    const bool q = b.qstep > 0;
+    if (b.staged) {
+      if (b.bs == 64) { if (q) ADCT_B8(true, true, 64); else ADCT_B8(false, true, 64); }
+      else { if (q) ADCT_B8(true, true, 256); else ADCT_B8(false, true, 256); }
+    } else {
+      if (b.bs == 64) { if (q) ADCT_B8(true, false, 64); else ADCT_B8(false, false, 64); }
+      else { if (q) ADCT_B8(true, false, 256); else ADCT_B8(false, false, 256); }
+    }
+  } else {
+#define ADCT_BJ(NN, Q, BS) bucket_jam<DT, KIND, NN, Q, BS><<<grid, BS, 0, s>>>(p)
+    const bool q = b.qstep > 0;
+    if (b.log2n == 4) {
+      if (b.bs == 128) { if (q) ADCT_BJ(16, true, 128); else ADCT_BJ(16, false, 128); }
+      else { if (q) ADCT_BJ(16, true, 256); else ADCT_BJ(16, false, 256); }
+    } else {
+      if (b.bs == 128) { if (q) ADCT_BJ(32, true, 128); else ADCT_BJ(32, false, 128); }
+      else { if (q) ADCT_BJ(32, true, 256); else ADCT_BJ(32, false, 256); }
+    }
+#undef ADCT_BJ
+  }
+#undef ADCT_B8
+}
+
+void launch_bucket(int dtype, const Bucket& b, const BucketParams& p, int first, int count,
+                   hipStream_t s) {
+  if (count <= 0) return;
+  if (dtype == ADCT_U8) {
+    if (b.kind == KIND_SIGN) launch_bucket_typed<DT_U8, KIND_SIGN>(b, p, first, count, s);
+    else launch_bucket_typed<DT_U8, KIND_ROUND>(b, p, first, count, s);
+  } else {
+    if (b.kind == KIND_SIGN) launch_bucket_typed<DT_I16, KIND_SIGN>(b, p, first, count, s);
+    else launch_bucket_typed<DT_I16, KIND_ROUND>(b, p, first, count, s);
+  }
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+struct adct_batch {
+  int dtype = 0;
+  int n_images = 0;
+  int64_t n_tus = 0;
+  int cus = 0;
+  std::string arch;
+  std::vector<int> tu_image;        // image of every TU in the sorted order
+  std::vector<int64_t> tu_kept;     // retained-coefficient offset, sorted order
+  std::vector<Bucket> buckets;
+  BImage* d_imgs = nullptr;
+  int2* d_pos = nullptr;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::tuple<const void*, void*, int32_t*, float*, uint64_t*, float*, hipStream_t> key{};
+  bool have_exec = false;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+  return set_error(ADCT_E_HIP, buf);
+}
+
+void drop_graph(adct_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->have_exec = false;
+}
+
+void free_plan(adct_batch* b) {
+  drop_graph(b);
+  for (Bucket& k : b->buckets)
+    if (k.d_items) (void)hipFree(k.d_items);
+  if (b->d_imgs) (void)hipFree(b->d_imgs);
+  if (b->d_pos) (void)hipFree(b->d_pos);
+  delete b;
+}
+
+// (Re)build the items of a bucket for its current workgroup size and upload them.
+hipError_t build_items(adct_batch* b, Bucket& k) {
+  const int cap = tus_per_item(k);
+  k.items.clear();
+  k.image_ranges.clear();
+  int64_t t = k.tu_begin;
+  while (t < k.tu_end) {
+    const int img = b->tu_image[t];
+    int64_t g = t;
+    while (g < k.tu_end && b->tu_image[g] == img) ++g;
+    const int first = static_cast<int>(k.items.size());
+    for (int64_t s = t; s < g; s += cap) {
+      BItem it;
+      it.image = img;
+      it.tu_begin = static_cast<int32_t>(s);
+      it.count = static_cast<int32_t>(std::min<int64_t>(cap, g - s));
+      it.pad = 0;
+      it.kept_base = b->tu_kept[s];
+      k.items.push_back(it);
+    }
+    k.image_ranges.emplace_back(first, static_cast<int>(k.items.size()));
+    t = g;
+  }
+  const size_t bytes = std::max<size_t>(1, k.items.size()) * sizeof(BItem);
+  if (bytes > k.d_cap) {
+    if (k.d_items) (void)hipFree(k.d_items);
+    k.d_items = nullptr;
+    k.d_cap = 0;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&k.d_items), bytes);
+    if (e != hipSuccess) return e;
+    k.d_cap = bytes;
+  }
+  if (k.items.empty()) return hipSuccess;
+  return hipMemcpy(k.d_items, k.items.data(), k.items.size() * sizeof(BItem),
+                   hipMemcpyHostToDevice);
+}
+
+BucketParams params_for(const adct_batch* b, const Bucket& k, const void* src, void* dst,
+                        int32_t* kept, float* scaled, uint64_t* sse) {
+  BucketParams p;
+  p.imgs = b->d_imgs;
+  p.items = k.d_items;
+  p.pos = b->d_pos;
+  p.src = src;
+  p.dst = dst;
+  p.kept = kept;
+  p.scaled = scaled;
+  p.sse = reinterpret_cast<unsigned long long*>(sse);
+  p.item_begin = 0;
+  p.t = k.tables;
+  return p;
+}
+
+hipError_t enqueue_run(const adct_batch* b, const void* src, void* dst, int32_t* kept,
+                       float* scaled, uint64_t* sse, float* psnr, int mode, hipStream_t s) {
+  const int nb = (b->n_images + 255) / 256;
+  auto* sse_dev = reinterpret_cast<unsigned long long*>(sse);
+  if (sse != nullptr && nb > 0) zero_u64<<<nb, 256, 0, s>>>(sse_dev, b->n_images);
+  for (const Bucket& k : b->buckets) {
+    const BucketParams p = params_for(b, k, src, dst, kept, scaled, sse);
+    if (mode == ADCT_RUN_PER_IMAGE) {
+      for (const auto& rg : k.image_ranges)
+        launch_bucket(b->dtype, k, p, rg.first, rg.second - rg.first, s);
+    } else {
+      launch_bucket(b->dtype, k, p, 0, static_cast<int>(k.items.size()), s);
+    }
+  }
+  if (psnr != nullptr && nb > 0)
+    psnr_kernel<<<nb, 256, 0, s>>>(sse_dev, b->d_imgs, psnr, b->n_images);
+  return hipGetLastError();
+}
+
+std::string tune_key(const adct_batch* b, const Bucket& k) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s:dt%d:n%d:k%d:q%d:st%d:tus%lld:img%d", b->arch.c_str(), b->dtype,
+           8 << (k.log2n - 3), k.kind, k.qstep, int(k.staged),
+           (long long)(k.tu_end - k.tu_begin), static_cast<int>(k.image_ranges.size()));
+  return buf;
+}
+
+int cache_lookup(const std::string& key) {
+  const char* path = getenv("ADCT_TUNE_CACHE");
+  if (path == nullptr || !*path) return 0;
+  FILE* f = fopen(path, "r");
+  if (!f) return 0;
+  char k[256];
+  int v = 0, found = 0;
+  while (fscanf(f, "%255s %d", k, &v) == 2)
+    if (key == k) found = v;
+  fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, int value) {
+  const char* path = getenv("ADCT_TUNE_CACHE");
+  if (path == nullptr || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d\n", key.c_str(), value);
+  fclose(f);
+}
+
+bool valid_bs(const Bucket& k, int bs) {
+  return k.log2n == 3 ? (bs == 64 || bs == 256) : (bs == 128 || bs == 256);
+}
+
+}  // namespace
+
+extern "C" {
+
+ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
+                               const adct_tu_desc_t* tus, int64_t n_tus, int dtype,
+                               int64_t* tu_kept_offset, int64_t* kept_words,
+                               adct_batch_t** plan) {
+  char msg[256];
+  if (plan == nullptr) return set_error(ADCT_E_ARG, "batch: null plan pointer");
+  *plan = nullptr;
+  if (dtype != ADCT_U8 && dtype != ADCT_I16) return set_error(ADCT_E_ARG, "batch: bad dtype");
+  if (n_images < 0 || n_tus < 0 || (n_images > 0 && images == nullptr) ||
+      (n_tus > 0 && tus == nullptr))
+    return set_error(ADCT_E_ARG, "batch: bad image or TU arrays");
+  if (n_tus > (int64_t(1) << 31) - 1) return set_error(ADCT_E_ARG, "batch: too many TUs");
+  const int esize = dtype == ADCT_U8 ? 1 : 2;
+  for (int i = 0; i < n_images; ++i) {
+    const adct_image_desc_t& im = images[i];
+    if (im.height <= 0 || im.width <= 0 || im.height % 8 || im.width % 8 || im.pitch < im.width) {
+      snprintf(msg, sizeof(msg), "batch: image %d has a bad shape", i);
+      return set_error(ADCT_E_SHAPE, msg);
+    }
+    if ((im.transform != ADCT_T1 && im.transform != ADCT_T2) || im.r < 1 || im.qstep < 0 ||
+        im.qstep > 4096 || im.src_offset < 0 || im.dst_offset < 0) {
+      snprintf(msg, sizeof(msg), "batch: image %d has a bad transform, r, qstep or offset", i);
+      return set_error(ADCT_E_ARG, msg);
+    }
+    if ((im.src_offset * esize) % 16 || (im.dst_offset * esize) % 16 ||
+        (static_cast<int64_t>(im.pitch) * esize) % 16) {
+      snprintf(msg, sizeof(msg), "batch: image %d offsets and pitch must be 16-byte aligned", i);
+      return set_error(ADCT_E_ALIGN, msg);
+    }
+  }
+  for (int64_t t = 0; t < n_tus; ++t) {
+    const adct_tu_desc_t& u = tus[t];
+    bool ok = u.image >= 0 && u.image < n_images && (u.n == 8 || u.n == 16 || u.n == 32) &&
+              u.x >= 0 && u.y >= 0;
+    if (ok) {
+      const adct_image_desc_t& im = images[u.image];
+      ok = u.x % u.n == 0 && u.y % u.n == 0 && u.x + u.n <= im.width && u.y + u.n <= im.height;
+    }
+    if (!ok) {
+      snprintf(msg, sizeof(msg), "batch: TU %lld is outside its image or misplaced", (long long)t);
+      return set_error(ADCT_E_SHAPE, msg);
+    }
+  }
+  auto* b = new adct_batch();
+  b->dtype = dtype;
+  b->n_images = n_images;
+  b->n_tus = n_tus;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) {
+    free_plan(b);
+    return hip_fail(e, "batch: device query");
+  }
+  b->cus = prop.multiProcessorCount;
+  b->arch = prop.gcnArchName;
+  for (char& c : b->arch)
+    if (c == ' ' || c == ':') c = '_';
+
+  // bucket key of a TU: (size, transform, step, staged)
+  auto key_of = [&](const adct_tu_desc_t& u) {
+    const adct_image_desc_t& im = images[u.image];
+    const int log2n = u.n == 8 ? 3 : (u.n == 16 ? 4 : 5);
+    const bool staged = u.n != 8 || std::min(im.r, 64) <= kStagedRB;
+    return std::make_tuple(log2n, im.transform, im.qstep, staged);
+  };
+  std::vector<int64_t> order(n_tus);
+  for (int64_t t = 0; t < n_tus; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t c) {
+    const auto ka = key_of(tus[a]), kc = key_of(tus[c]);
+    if (ka != kc) return ka < kc;
+    return tus[a].image < tus[c].image;
+  });
+  std::vector<int2> pos(n_tus);
+  b->tu_image.resize(n_tus);
+  b->tu_kept.resize(n_tus);
+  int64_t kept = 0;
+  int64_t t = 0;
+  while (t < n_tus) {
+    const auto key = key_of(tus[order[t]]);
+    Bucket k;
+    k.log2n = std::get<0>(key);
+    k.kind = std::get<1>(key);
+    k.qstep = std::get<2>(key);
+    k.staged = std::get<3>(key);
+    k.bs = 256;
+    if (int st = build_tables_for(k.kind, 8 << (k.log2n - 3), k.qstep, &k.tables)) {
+      free_plan(b);
+      return st;
+    }
+    k.tu_begin = t;
+    while (t < n_tus && key_of(tus[order[t]]) == key) {
+      const adct_tu_desc_t& u = tus[order[t]];
+      pos[t] = make_int2(u.x, u.y);
+      b->tu_image[t] = u.image;
+      b->tu_kept[t] = kept;
+      if (tu_kept_offset) tu_kept_offset[order[t]] = kept;
+      kept += std::min(images[u.image].r, u.n * u.n);
+      ++t;
+    }
+    k.tu_end = t;
+    b->buckets.push_back(k);
+  }
+  if (kept_words) *kept_words = kept;
+  std::vector<BImage> himgs(n_images);
+  for (int i = 0; i < n_images; ++i) {
+    himgs[i].src_off = images[i].src_offset;
+    himgs[i].dst_off = images[i].dst_offset;
+    himgs[i].npix = static_cast<int64_t>(images[i].height) * images[i].width;
+    himgs[i].pitch = images[i].pitch;
+    himgs[i].r = images[i].r;
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&b->d_imgs),
+                std::max<size_t>(1, himgs.size()) * sizeof(BImage));
+  if (e == hipSuccess && !himgs.empty())
+    e = hipMemcpy(b->d_imgs, himgs.data(), himgs.size() * sizeof(BImage), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&b->d_pos), std::max<size_t>(1, pos.size()) * sizeof(int2));
+  if (e == hipSuccess && !pos.empty())
+    e = hipMemcpy(b->d_pos, pos.data(), pos.size() * sizeof(int2), hipMemcpyHostToDevice);
+  for (Bucket& k : b->buckets) {
+    if (e != hipSuccess) break;
+    if (int cached = cache_lookup(tune_key(b, k)))
+      if (valid_bs(k, cached)) k.bs = cached;
+    e = build_items(b, k);
+  }
+  if (e != hipSuccess) {
+    free_plan(b);
+    return hip_fail(e, "batch: upload");
+  }
+  *plan = b;
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_destroy(adct_batch_t* plan) {
+  if (plan == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
+  free_plan(plan);
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_info(const adct_batch_t* b, int64_t* out) {
+  if (b == nullptr || out == nullptr) return set_error(ADCT_E_ARG, "batch: null argument");
+  int64_t items = 0, by[3] = {0, 0, 0};
+  for (const Bucket& k : b->buckets) {
+    items += static_cast<int64_t>(k.items.size());
+    by[k.log2n - 3] += static_cast<int64_t>(k.items.size());
+  }
+  out[0] = b->n_images;
+  out[1] = b->n_tus;
+  out[2] = items;
+  out[3] = by[0];
+  out[4] = by[1];
+  out[5] = by[2];
+  out[6] = static_cast<int64_t>(b->buckets.size());
+  out[7] = b->cus;
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_set_shape(adct_batch_t* b, int bs8, int bs_jam) {
+  if (b == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
+  if ((bs8 != 64 && bs8 != 256) || (bs_jam != 128 && bs_jam != 256))
+    return set_error(ADCT_E_ARG, "batch: workgroup sizes are 64/256 (8x8) and 128/256 (16/32)");
+  drop_graph(b);
+  for (Bucket& k : b->buckets) {
+    const int bs = k.log2n == 3 ? bs8 : bs_jam;
+    if (k.bs == bs) continue;
+    k.bs = bs;
+    if (hipError_t e = build_items(b, k); e != hipSuccess) return hip_fail(e, "batch: items");
+  }
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_run(adct_batch_t* b, const void* d_src, void* d_dst, int32_t* d_kept,
+                            float* d_scaled, uint64_t* d_sse, float* d_psnr, int mode,
+                            adct_stream_t stream) {
+  if (b == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
+  if (mode != ADCT_RUN_BATCHED && mode != ADCT_RUN_GRAPH && mode != ADCT_RUN_PER_IMAGE)
+    return set_error(ADCT_E_ARG, "batch: bad run mode");
+  if (d_psnr != nullptr && d_sse == nullptr)
+    return set_error(ADCT_E_ARG, "batch: d_psnr needs d_sse");
+  if (b->n_tus > 0 && d_src == nullptr) return set_error(ADCT_E_ARG, "batch: null source");
+  if ((reinterpret_cast<uintptr_t>(d_src) % 16) || (reinterpret_cast<uintptr_t>(d_dst) % 16) ||
+      (reinterpret_cast<uintptr_t>(d_kept) % 4) || (reinterpret_cast<uintptr_t>(d_scaled) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_sse) % 8) || (reinterpret_cast<uintptr_t>(d_psnr) % 4))
+    return set_error(ADCT_E_ALIGN, "batch: misaligned buffer");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mode == ADCT_RUN_GRAPH && s == nullptr)
+    return set_error(ADCT_E_ARG, "batch: graph capture needs a non-null stream");
+  hipError_t e;
+  if (mode != ADCT_RUN_GRAPH) {
+    e = enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, d_psnr, mode, s);
+    if (e != hipSuccess) return hip_fail(e, "batch: launch");
+    return set_error(ADCT_OK, "");
+  }
+  const auto key = std::make_tuple(d_src, d_dst, d_kept, d_scaled, d_sse, d_psnr, s);
+  if (!b->have_exec || b->key != key) {
+    drop_graph(b);
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "batch: begin capture");
+    const hipError_t le =
+        enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, d_psnr, ADCT_RUN_BATCHED, s);
+    e = hipStreamEndCapture(s, &b->graph);
+    if (le != hipSuccess) return hip_fail(le, "batch: capture launch");
+    if (e != hipSuccess) return hip_fail(e, "batch: end capture");
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch: instantiate");
+    b->key = key;
+    b->have_exec = true;
+  }
+  e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_tune(adct_batch_t* b, const void* d_src, void* d_dst, int32_t* d_kept,
+                             float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen) {
+  if (b == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  drop_graph(b);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "batch: tune events");
+  int nb = 0;
+  for (Bucket& k : b->buckets) {
+    const std::string key = tune_key(b, k);
+    int best_bs = k.bs;
+    if (int cached = cache_lookup(key); cached && valid_bs(k, cached)) {
+      best_bs = cached;
+    } else {
+      float best = 1e30f;
+      const int cands8[] = {64, 256}, candsj[] = {128, 256};
+      const int* cands = k.log2n == 3 ? cands8 : candsj;
+      for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        k.bs = cands[c];
+        e = build_items(b, k);
+        if (e != hipSuccess) break;
+        const BucketParams p = params_for(b, k, d_src, d_dst, d_kept, d_scaled, d_sse);
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess) {
+            launch_bucket(b->dtype, k, p, 0, static_cast<int>(k.items.size()), s);
+            e = hipGetLastError();
+          }
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) t_min = std::min(t_min, ms);  // the first run warms up
+        }
+        if (t_min < best) {
+          best = t_min;
+          best_bs = cands[c];
+        }
+      }
+      if (e == hipSuccess) cache_store(key, best_bs);
+    }
+    if (e != hipSuccess) break;
+    k.bs = best_bs;
+    e = build_items(b, k);
+    if (chosen) chosen[nb] = best_bs;
+    ++nb;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "batch: tune");
+  return set_error(ADCT_OK, "");
+}
+
+}  // extern "C"

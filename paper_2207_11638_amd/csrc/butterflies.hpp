@@ -22,9 +22,9 @@
 
 #if defined(__HIPCC__) || defined(__HIP__)
 #include <hip/hip_runtime.h>
-#define ADCT_HD __host__ __device__ __forceinline__
+#define ADCT_HD __host__ __device__ __forceinline__ constexpr
 #else
-#define ADCT_HD inline
+#define ADCT_HD inline constexpr
 #endif
 
 namespace adct {
@@ -42,7 +42,7 @@ ADCT_HD void fwd8(int (&x)[8]) {
   const int z4 = y7, z5 = y5 + y6, z6 = y6 - y5, z7 = y4;
   // M3 = diag(C~(alpha, gamma), A2)
   const int w0 = z0 + z1, w1 = z0 - z1;
-  int w2, w3;
+  int w2 = 0, w3 = 0;
   if constexpr (KIND == KIND_SIGN) {  // gamma = (1, 1)
     w2 = z3 - z2;
     w3 = z2 + z3;
@@ -53,7 +53,7 @@ ADCT_HD void fwd8(int (&x)[8]) {
   const int w4 = z4 + z5, w5 = z4 - z5, w6 = z7 - z6, w7 = z6 + z7;
   // M2 = diag(P4, A1(beta))
   const int v0 = w0, v1 = w3, v2 = w1, v3 = w2;
-  int v4, v7;
+  int v4 = 0, v7 = 0;
   if constexpr (KIND == KIND_SIGN) {  // beta = (1, 1, 1, 1)
     v4 = w4 + w7;
     v7 = w4 - w7;
@@ -81,7 +81,7 @@ ADCT_HD void inv8(int (&X)[8]) {
   const int v4 = X[1], v5 = X[5], v6 = X[3], v7 = X[7];
   // 2 M2^-1 = diag(2 P4^T, 2 A1^-1)
   const int w0 = 2 * v0, w1 = 2 * v2, w2 = 2 * v3, w3 = 2 * v1;
-  int w4, w7;
+  int w4 = 0, w7 = 0;
   if constexpr (KIND == KIND_SIGN) {  // 2 A1^-1 = A1
     w4 = v4 + v7;
     w7 = v4 - v7;
@@ -92,7 +92,7 @@ ADCT_HD void inv8(int (&X)[8]) {
   const int w5 = v5 + v6, w6 = v5 - v6;
   // 2 M3^-1
   const int z0 = w0 + w1, z1 = w0 - w1;
-  int z2, z3;
+  int z2 = 0, z3 = 0;
   if constexpr (KIND == KIND_SIGN) {
     z2 = w3 - w2;
     z3 = w2 + w3;
@@ -122,7 +122,7 @@ ADCT_HD void fwdN(int (&x)[N]) {
     fwd8<KIND>(x);
   } else {
     constexpr int H = N / 2;
-    int u[H], w[H];
+    int u[H] = {}, w[H] = {};
 #pragma unroll
     for (int i = 0; i < H; ++i) {
       u[i] = x[i] + x[N - 1 - i];       // top half of M_add
@@ -145,7 +145,7 @@ ADCT_HD void invN(int (&X)[N]) {
     inv8<KIND>(X);
   } else {
     constexpr int H = N / 2;
-    int p[H], q[H];
+    int p[H] = {}, q[H] = {};
 #pragma unroll
     for (int k = 0; k < H; ++k) {       // M_per^T
       p[k] = X[2 * k];
@@ -165,7 +165,7 @@ ADCT_HD void invN(int (&X)[N]) {
 // Position of coefficient (v, u) (v vertical, u horizontal frequency) in the
 // JPEG zig-zag scan of an N x N block: anti-diagonals d = v + u in increasing
 // order, odd d scanned with increasing v, even d with decreasing v.
-ADCT_HD constexpr int zz_pos(int n, int v, int u) {
+ADCT_HD int zz_pos(int n, int v, int u) {
   const int d = v + u;
   if (d < n) {
     const int base = d * (d + 1) / 2;
@@ -174,6 +174,45 @@ ADCT_HD constexpr int zz_pos(int n, int v, int u) {
   const int tail = (2 * n - 1 - d) * (2 * n - d) / 2;
   const int base = n * n - tail;
   return base + ((d & 1) ? v - (d - n + 1) : (n - 1 - v));
+}
+
+// Row classes of T_N: the distinct values of diag(T_N T_N^T), sorted
+// increasingly, numbered 0, 1, ...; cls[v] is the class of row v.  Computed
+// from the forward butterfly itself (at compile time in the kernels), so the
+// host tables and the kernels agree by construction.
+template <int N>
+struct RowClasses {
+  int cls[N];
+  long long value[4];
+  int count;
+};
+
+template <int KIND, int N>
+ADCT_HD RowClasses<N> row_classes() {
+  long long d[N] = {};
+  for (int j = 0; j < N; ++j) {
+    int e[N] = {};
+    e[j] = 1;
+    fwdN<KIND, N>(e);
+    for (int v = 0; v < N; ++v) d[v] += static_cast<long long>(e[v]) * e[v];
+  }
+  RowClasses<N> rc{};
+  rc.count = 0;
+  for (int v = 0; v < N; ++v) {       // insertion of distinct values, kept sorted
+    bool seen = false;
+    for (int c = 0; c < rc.count; ++c) seen = seen || rc.value[c] == d[v];
+    if (seen) continue;
+    int c = rc.count++;
+    while (c > 0 && rc.value[c - 1] > d[v]) {
+      rc.value[c] = rc.value[c - 1];
+      --c;
+    }
+    rc.value[c] = d[v];
+  }
+  for (int v = 0; v < N; ++v)
+    for (int c = 0; c < rc.count; ++c)
+      if (rc.value[c] == d[v]) rc.cls[v] = c;
+  return rc;
 }
 
 // Rounded division by 2^S with the paper's round() (half away from zero):

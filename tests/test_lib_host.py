@@ -108,3 +108,34 @@ def test_python_front_end_refuses_host_tensors():
         adct.compress(x, 1, 8, 10)
     with pytest.raises(ValueError):
         adct.fwd2d(x, 1, 8)
+
+
+def test_batch_plan_validation_before_gpu(lib):
+    import numpy as np
+    descs = np.zeros(1, dtype=adct.IMAGE_DESC)
+    descs[0] = (0, 0, 64, 64, 64, 1, 10, 0)
+    tus = np.zeros(1, dtype=adct.TU_DESC)
+    tus[0] = (0, 0, 0, 8)
+    h = C.c_void_p()
+    w = C.c_int64()
+
+    def create(d, t, dtype=0):
+        return lib.adct_batch_create(d.ctypes.data, len(d), t.ctypes.data, len(t), dtype,
+                                     None, C.byref(w), C.byref(h))
+
+    bad = tus.copy(); bad[0] = (0, 60, 0, 8)        # outside the image
+    assert create(descs, bad) == -2
+    bad[0] = (0, 8, 0, 16)                          # not aligned to its size
+    assert create(descs, bad) == -2
+    bad[0] = (1, 0, 0, 8)                           # no such image
+    assert create(descs, bad) == -2
+    bad[0] = (0, 0, 0, 12)                          # bad size
+    assert create(descs, bad) == -2
+    d2 = descs.copy(); d2[0]["height"] = 60         # not a multiple of 8
+    assert create(d2, tus) == -2
+    d2 = descs.copy(); d2[0]["transform"] = 3
+    assert create(d2, tus) == -1
+    d2 = descs.copy(); d2[0]["src_offset"] = 4      # not 16-byte aligned
+    assert create(d2, tus) == -3
+    assert create(descs, tus, dtype=5) == -1
+    assert lib.adct_batch_run(None, None, None, None, None, None, None, 0, None) == -1
