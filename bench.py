@@ -32,6 +32,7 @@ KINDS = (1, 2)
 N = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_compress8_c1.json")
 KERNEL_SOURCES = ("paper_2207_11638_amd/csrc/kernels_n8.hip",
+                  "paper_2207_11638_amd/csrc/tile8.hpp",
                   "paper_2207_11638_amd/csrc/butterflies.hpp")
 
 
@@ -152,7 +153,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--images", type=int, default=1024)
+    ap.add_argument("--workload", choices=("c1", "c3", "plain"), default="c1",
+                    help="c1: the 1024 x 2048^2 sweep (default); c3: the ragged batch; "
+                         "plain: one fused configuration (--n, --transform, --r, --qstep)")
+    ap.add_argument("--n", type=int, default=8)
+    ap.add_argument("--transform", type=int, default=2)
+    ap.add_argument("--r", type=int, default=10)
+    ap.add_argument("--qstep", type=int, default=0)
+    ap.add_argument("--dtype", choices=("u8", "i16"), default="u8")
+    ap.add_argument("--images", type=int, default=None)
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -170,16 +179,26 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    if args.workload == "c3":
+        run_c3(args)
+    elif args.workload == "plain":
+        run_plain(args)
+    else:
+        run_c1(args)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_c1(args):
     import numpy as np
     import torch
 
     import paper_2207_11638_amd as adct
     import synth
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    b, h, w = args.images, args.size, args.size
+    b, h, w = args.images or 1024, args.size, args.size
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     imgs, rhos = synth.ar1_batch(b, h, w, workers=args.gen_workers)
@@ -306,6 +325,207 @@ def main():
         "kernels": kernels,
         "parity_sample": check,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------- one config
+def run_plain(args):
+    """One fused configuration over a batch of equal images (uint8 AR(1) or
+    int16 Laplacian residuals), outputs kept + scaled + recon + sse."""
+    import torch
+
+    import paper_2207_11638_amd as adct
+    import synth
+
+    b, h, w, n, r = args.images or 256, args.size, args.size, args.n, args.r
+    dev = torch.device("cuda:0")
+    if args.dtype == "u8":
+        imgs, _ = synth.ar1_batch(b, h, w, workers=args.gen_workers)
+        x = torch.from_numpy(imgs).to(dev)
+    else:
+        x = torch.stack([torch.from_numpy(synth.laplace_residual(h, w, seed=2000 + i))
+                         for i in range(b)]).to(dev)
+    tiles = b * (h // n) * (w // n)
+    kept = torch.empty((b, h // n, w // n, r), dtype=torch.int32, device=dev)
+    scaled = torch.empty((b, h // n, w // n, r), dtype=torch.float32, device=dev)
+    recon = torch.empty_like(x)
+    sse = torch.zeros(b, dtype=torch.uint64, device=dev)
+
+    def step():
+        adct.compress(x, args.transform, n, r, args.qstep, kept=kept, scaled=scaled, recon=recon,
+                      sse=sse)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    z = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        step()
+    z.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(z) / args.steps
+    esize = x.element_size()
+    algo = b * h * w * 2 * esize + tiles * r * 8 + b * 8
+    achieved = algo / ms / 1e6
+    print(json.dumps({"metric": METRIC, "value": round(b * h * w / ms / 1e6, 2),
+                      "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(ms, 4),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "int32", "data": "synthetic",
+                      "config": {"workload": f"plain: {b} x {h}x{w} {args.dtype}, N={n}, "
+                                             f"T{args.transform}, r={r}, qstep={args.qstep}"},
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                      "cpu_baseline": None}), flush=True)
+
+
+# --------------------------------------------------------------- ragged batch
+def run_c3(args):
+    """10000 images with log-normal sides in [64, 4096] (multiples of 8), AR(1)
+    content with rho ~ U[0.85, 0.98], each split by a seeded HEVC-style
+    quadtree (32x32 units, split probability 0.4 per level, forced splits at
+    the border) into 8/16/32 TUs; T1/T2 alternate by image, r ~ U{6..28} per
+    image.  One step = one pass over every TU (retained int32 coefficients,
+    reconstruction, error energy and PSNR per image).  Timed three ways: one
+    launch per bucket (the batched form), its graph replay, and one launch per
+    image and bucket (the per-image baseline)."""
+    import numpy as np
+    import torch
+
+    import paper_2207_11638_amd as adct
+    import synth
+    from paper_2207_11638_amd import ragged
+
+    n = args.images or 10000
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sizes = synth.ragged_sizes(n, seed=3000)
+    hs, ws = sizes[:, 0], sizes[:, 1]
+    rhos = np.array([synth.rng_for(1_003_000 + i).uniform(0.85, 0.98) for i in range(n)])
+    pitches = (ws + 15) // 16 * 16
+    offsets = np.zeros(n, dtype=np.int64)
+    off = 0
+    for i in range(n):
+        off = (off + 255) // 256 * 256
+        offsets[i] = off
+        off += int(pitches[i] * hs[i])
+    total = (off + 255) // 256 * 256
+    arena = synth.ar1_arena(offsets, hs, ws, pitches, 3000 + np.arange(n), rhos, total,
+                            workers=args.gen_workers)
+    rs = synth.rng_for(3002).integers(6, 29, size=n)
+    descs = np.zeros(n, dtype=adct.IMAGE_DESC)
+    descs["src_offset"] = offsets
+    descs["dst_offset"] = offsets
+    descs["height"], descs["width"], descs["pitch"] = hs, ws, pitches
+    descs["transform"] = 1 + np.arange(n) % 2
+    descs["r"] = rs
+    tus = ragged.tu_table([synth.quadtree_tus_fast(int(hs[i]), int(ws[i]),
+                                                   synth.rng_for(4_000_000 + i))
+                           for i in range(n)])
+    npx = int((hs * ws).sum())
+    log(f"generated {n} images ({npx / 1e9:.2f} Gpx) and {len(tus)} TUs in "
+        f"{time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    plan = adct.BatchPlan(descs, tus, torch.uint8)
+    info = plan.info()
+    log(f"plan built in {time.perf_counter() - t0:.1f} s: {info}")
+    src = torch.from_numpy(arena).to(dev)
+    del arena
+    dst = torch.zeros_like(src)
+    kept = torch.empty(max(1, plan.kept_words), dtype=torch.int32, device=dev)
+    sse = torch.zeros(n, dtype=torch.uint64, device=dev)
+    psnr = torch.zeros(n, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    chosen = plan.tune(src, dst, kept, None, sse)
+    log(f"tuned workgroup sizes per bucket: {chosen.tolist()}")
+
+    def timed(mode, steps, warmup, stream=None):
+        ctx = torch.cuda.stream(stream) if stream is not None else None
+        if ctx:
+            ctx.__enter__()
+        try:
+            for _ in range(warmup):
+                plan.run(src, dst, kept, None, sse, psnr, mode=mode)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                plan.run(src, dst, kept, None, sse, psnr, mode=mode)
+            z.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(z) / steps
+        finally:
+            if ctx:
+                ctx.__exit__(None, None, None)
+
+    ms_batched = timed("batched", args.steps, args.warmup)
+    ms_graph = timed("graph", args.steps, max(1, args.warmup), torch.cuda.Stream())
+    ms_per_image = timed("per_image", 1, 1)
+    log(f"ms per pass: batched {ms_batched:.2f}, graph {ms_graph:.2f}, "
+        f"per-image launches {ms_per_image:.2f}")
+
+    check = None
+    if not args.no_check:
+        from oracle import pipeline as P
+        plan.run(src, dst, kept, None, sse, psnr, mode="batched")
+        torch.cuda.synchronize()
+        dst_h = dst.cpu().numpy()
+        kept_h = kept.cpu().numpy()
+        sse_h = sse.cpu().numpy().astype(np.int64)
+        bad = 0
+        for i in (0, n // 2, n - 1):
+            img = synth.ar1_arena([0], [hs[i]], [ws[i]], [ws[i]], [3000 + i], [rhos[i]],
+                                  int(hs[i] * ws[i])).reshape(hs[i], ws[i])
+            rec = ragged.unpack_image(dst_h, descs[i])
+            e = 0
+            for t in np.nonzero(tus["image"] == i)[0]:
+                x, y, nn = int(tus[t]["x"]), int(tus[t]["y"]), int(tus[t]["n"])
+                r = min(int(rs[i]), nn * nn)
+                out = P.compress(img[y:y + nn, x:x + nn], int(descs[i]["transform"]), nn, r)
+                o = int(plan.tu_kept_offset[t])
+                bad += int(not np.array_equal(kept_h[o:o + r], out["kept"].reshape(-1)))
+                bad += int(not np.array_equal(rec[y:y + nn, x:x + nn], out["recon"]))
+                e += out["sse"]
+            bad += int(e != sse_h[i])
+        check = "ok" if bad == 0 else f"{bad} mismatches"
+        log(f"sampled parity vs oracle (images 0, {n // 2}, {n - 1}, every TU): {check}")
+
+    algo = 2 * npx + 4 * plan.kept_words + 12 * n
+    achieved = algo / ms_batched / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(npx / ms_batched / 1e6, 2),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded ragged AR(1) uint8 images, quadtree TUs)",
+        "config": {"workload": f"ragged batch: {n} AR(1) images ({npx / 1e9:.2f} Gpx), sides "
+                               "log-normal in [64, 4096], 8/16/32 quadtree TUs (p=0.4), "
+                               "T1/T2, r in 6..28",
+                   "images": n, "tus": int(len(tus)), "pixels": npx},
+        "batched_vs_per_image": {"batched_ms": round(ms_batched, 3),
+                                 "graph_ms": round(ms_graph, 3),
+                                 "per_image_ms": round(ms_per_image, 3),
+                                 "speedup": round(ms_per_image / ms_batched, 2),
+                                 "per_image_gpixel_s": round(npx / ms_per_image / 1e6, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "bucket8 / bucket_jam (one launch per bucket)"},
+        "plan": info,
+        "tuned_block_sizes": chosen.tolist(),
+        "parity_sample": check,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

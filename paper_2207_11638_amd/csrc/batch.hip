@@ -1,7 +1,8 @@
 // Ragged batches: transform units (TUs) of mixed sizes from many images.
 //
 // Plan.  TUs are split into buckets by (size, transform, quantiser step, and
-// for 8x8 TUs whether r <= 32) and sorted by image inside each bucket.  A
+// for 8x8 TUs whether r <= 32) and sorted by image and raster position inside
+// each bucket.  A
 // bucket is processed by one launch of a kernel specialised for it, so each
 // kernel keeps the register footprint of the plain kernels and its constant
 // tables travel as kernel arguments.  A work item is a run of TUs of one image
@@ -437,10 +438,17 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
   };
   std::vector<int64_t> order(n_tus);
   for (int64_t t = 0; t < n_tus; ++t) order[t] = t;
+  // inside a bucket: by image, then raster order (y, x), so that the TUs of
+  // a workgroup are as often as possible horizontal neighbours and its row
+  // loads/stores form contiguous runs
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t c) {
     const auto ka = key_of(tus[a]), kc = key_of(tus[c]);
     if (ka != kc) return ka < kc;
-    return tus[a].image < tus[c].image;
+    const adct_tu_desc_t& x = tus[a];
+    const adct_tu_desc_t& y = tus[c];
+    if (x.image != y.image) return x.image < y.image;
+    if (x.y != y.y) return x.y < y.y;
+    return x.x < y.x;
   });
   std::vector<int2> pos(n_tus);
   b->tu_image.resize(n_tus);

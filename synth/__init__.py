@@ -31,6 +31,8 @@ __all__ = [
     "laplace_residual",
     "residual_frame_planes",
     "quadtree_tus",
+    "quadtree_tus_fast",
+    "ar1_arena",
     "ragged_sizes",
     "poisson_arrivals",
     "serving_requests",
@@ -199,6 +201,86 @@ def quadtree_tus(h: int, w: int, rng: np.random.Generator, p_split: float = 0.4,
         for cx in range(0, w, ctu):
             visit(cx, cy, ctu)
     return np.asarray(out, dtype=np.int32).reshape(-1, 3)
+
+
+def quadtree_tus_fast(h: int, w: int, rng: np.random.Generator, p_split: float = 0.4,
+                      ctu: int = 32, min_tu: int = 8) -> np.ndarray:
+    """Vectorised form of ``quadtree_tus`` (same model, different draw order):
+    level by level, every block that lies inside the image splits with
+    probability ``p_split`` and every block crossing the border splits; blocks
+    entirely outside are dropped.  Returns int32 rows (x, y, size)."""
+    assert h % min_tu == 0 and w % min_tu == 0
+    ys, xs = np.meshgrid(np.arange(0, h, ctu), np.arange(0, w, ctu), indexing="ij")
+    blocks = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int64)
+    size = ctu
+    out = []
+    while len(blocks):
+        x, y = blocks[:, 0], blocks[:, 1]
+        inside = (x + size <= w) & (y + size <= h)
+        if size > min_tu:
+            split = ~inside | (rng.random(len(blocks)) < p_split)
+        else:
+            split = np.zeros(len(blocks), dtype=bool)
+        keep = blocks[~split]
+        if len(keep):
+            out.append(np.column_stack([keep, np.full(len(keep), size)]))
+        if size == min_tu:
+            break
+        half = size // 2
+        kids = blocks[split]
+        kids = np.concatenate([kids + [0, 0], kids + [half, 0], kids + [0, half],
+                               kids + [half, half]])
+        kids = kids[(kids[:, 0] < w) & (kids[:, 1] < h)]
+        blocks, size = kids, half
+    if not out:
+        return np.zeros((0, 3), dtype=np.int32)
+    return np.concatenate(out).astype(np.int32)
+
+
+def _fill_images(args):
+    name, total, jobs = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        arena = np.ndarray((total,), dtype=np.uint8, buffer=shm.buf)
+        for off, h, w, pitch, seed, rho in jobs:
+            rng = rng_for(seed)
+            y = ar1_field(h, w, rho, rng)
+            img = np.clip(_round_half_away(128.0 + 40.0 * y), 0, 255).astype(np.uint8)
+            arena[off:off + pitch * h].reshape(h, pitch)[:, :w] = img
+        del arena
+        return len(jobs)
+    finally:
+        shm.close()
+
+
+def ar1_arena(offsets, heights, widths, pitches, seeds, rhos, total: int, workers: int = 1):
+    """Fill a flat uint8 arena with AR(1) images (sigma 40, mean 128) at the
+    given pixel offsets, image i drawn from seed ``seeds[i]`` with ``rhos[i]``.
+    Padding between rows and images is zero."""
+    jobs = list(zip(map(int, offsets), map(int, heights), map(int, widths), map(int, pitches),
+                    map(int, seeds), map(float, rhos)))
+    if workers <= 1:
+        arena = np.zeros(total, dtype=np.uint8)
+        for off, h, w, pitch, seed, rho in jobs:
+            y = ar1_field(h, w, rho, rng_for(seed))
+            img = np.clip(_round_half_away(128.0 + 40.0 * y), 0, 255).astype(np.uint8)
+            arena[off:off + pitch * h].reshape(h, pitch)[:, :w] = img
+        return arena
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=max(1, total))
+    try:
+        np.ndarray((total,), dtype=np.uint8, buffer=shm.buf)[:] = 0
+        # largest images first so that the pool stays balanced
+        order = sorted(range(len(jobs)), key=lambda i: -jobs[i][1] * jobs[i][2])
+        chunks = [[jobs[i] for i in order[k::workers * 8]] for k in range(workers * 8)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            pool.map(_fill_images, [(shm.name, total, c) for c in chunks if c])
+        return np.ndarray((total,), dtype=np.uint8, buffer=shm.buf).copy()
+    finally:
+        shm.close()
+        shm.unlink()
 
 
 def ragged_sizes(n: int, seed: int, median: float = 512.0, sigma: float = 0.75,
