@@ -40,8 +40,42 @@ struct PassParams {
   Geom g;
   int r;
   int qstep;
+  int gpw;                // compress: tile groups per workgroup along a tile row
   Tables t;
 };
+
+// Tile groups one fused workgroup walks along its tile row.  Every workgroup
+// adds its image's error energy with one 64-bit atomic, and all workgroups
+// resident at a time work on one or two images, so those atomics meet on one
+// or two addresses; walking several groups divides their number.  Capped at 8
+// and lowered while the grid would hold fewer than 8192 workgroups.
+inline int groups_per_wg(int groups_x, int64_t rows) {
+  int gpw = groups_x < 8 ? groups_x : 8;
+  while (gpw > 1 && static_cast<int64_t>((groups_x + gpw - 1) / gpw) * rows < 8192) gpw >>= 1;
+  return gpw < 1 ? 1 : gpw;
+}
+
+// Sum e over the BS threads of a workgroup and add it to *sse with one
+// atomic (none when the sum is zero).  red: BS / 64 words of LDS (unused for
+// a single wave).  Every thread of the workgroup calls it.
+template <int BS>
+__device__ __forceinline__ void block_add_sse(unsigned long long* sse, unsigned long long e,
+                                              unsigned long long* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if constexpr (BS == 64) {
+    if (threadIdx.x == 0 && e != 0) atomicAdd(sse, e);
+  } else {
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long sum = 0;
+#pragma unroll
+      for (int w = 0; w < BS / 64; ++w) sum += red[w];
+      if (sum != 0) atomicAdd(sse, sum);
+    }
+  }
+}
 
 enum class Mode : int { Compress = 0, Forward = 1, Inverse = 2, Decompress = 3 };
 

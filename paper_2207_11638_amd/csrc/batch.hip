@@ -86,6 +86,7 @@ __global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
   constexpr int RB = STAGED ? kStagedRB : 64;
   constexpr int esize = DT == DT_U8 ? 1 : 2;
   __shared__ int S[STAGED ? BS * t8::row_stride(kStagedRB) : 1];
+  __shared__ unsigned long long red[BS / 64];
   const BItem it = p.items[p.item_begin + blockIdx.x];
   const BImage im = p.imgs[it.image];
   const int w = threadIdx.x / kWave;
@@ -105,9 +106,10 @@ __global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
   const int64_t kb = it.kept_base + static_cast<int64_t>(w) * kWave * r;
   io.kept = p.kept != nullptr ? p.kept + kb : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + kb : nullptr;
-  io.sse = p.sse != nullptr ? p.sse + it.image : nullptr;
-  t8::compress_wave<KIND, DT, RB, QUANT, STAGED>(S + (STAGED ? w * kWave * t8::row_stride(RB) : 0),
-                                                 p.t, io);
+  io.sse = p.sse != nullptr;
+  const unsigned long long e = t8::compress_wave<KIND, DT, RB, QUANT, STAGED>(
+      S + (STAGED ? w * kWave * t8::row_stride(RB) : 0), p.t, io);
+  if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
 }
 
 // 16x16 / 32x32 TUs: BS / N tiles per workgroup.
@@ -116,10 +118,11 @@ __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
   constexpr int esize = DT == DT_U8 ? 1 : 2;
   using C = jam::Cfg<N, BS>;
   __shared__ int S[C::WORDS];
-  __shared__ jam::Shared sh;
-  jam::load_tables(sh, p.t, N);
+  __shared__ jam::Shared<N> sh;
+  __shared__ unsigned long long red[BS / 64];
   const BItem it = p.items[p.item_begin + blockIdx.x];
   const BImage im = p.imgs[it.image];
+  jam::load_tables<N, BS>(sh, p.t, min(im.r, N * N));
   const int k = threadIdx.x % C::TPW;
   jam::GroupIO io;
   io.src = offset_px(p.src, im.src_off, esize);
@@ -134,8 +137,9 @@ __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
   io.r = r;
   io.kept = p.kept != nullptr ? p.kept + it.kept_base : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + it.kept_base : nullptr;
-  io.sse = p.sse != nullptr ? p.sse + it.image : nullptr;
-  jam::compress_group<KIND, N, DT, QUANT, BS>(S, sh, io);
+  io.sse = p.sse != nullptr;
+  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS>(S, sh, io);
+  if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
 }
 
 __global__ void zero_u64(unsigned long long* p, int n) {

@@ -41,22 +41,42 @@ struct Cfg {
 constexpr int kBlock = 256;
 constexpr int kMaxWords = Cfg<32>::WORDS;
 
-// Constant tables of one (transform, N, qstep), staged in LDS.
+// Constant tables of one (transform, N, qstep, r), staged in LDS.
+//   zz[p]  (p < r): zig-zag position p of a tile, as its word offset
+//          v (N+1) + u in the padded [v][u] layout (low 16 bits) and its
+//          class-table entry cls[v] * 4 + cls[u] (high bits);
+//   cnt[u]: rows kept in column u (the zig-zag prefix keeps rows 0..cnt-1).
+template <int N>
 struct Shared {
   int32_t mq[16];
   int32_t dq[16];
   float s2[16];
-  int32_t cls[32];
+  int32_t cls[N];
+  int32_t cnt[N];
+  int32_t zz[N * N];
 };
 
-__device__ __forceinline__ void load_tables(Shared& sh, const Tables& t, int n) {
+// Fill the tables of one workgroup.  The zonal part depends on r only; it
+// reads the row classes from the kernel argument, so no barrier is needed
+// before it.  The caller synchronises before the first use.
+template <int N, int BS>
+__device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int r) {
   const int i = threadIdx.x;
   if (i < 16) {
     sh.mq[i] = t.mq[i];
     sh.dq[i] = t.dq[i];
     sh.s2[i] = t.s2[i];
   }
-  if (i < n) sh.cls[i] = t.cls[i];
+  if (i < N) sh.cls[i] = t.cls[i];
+#pragma unroll
+  for (int idx = i; idx < N * N; idx += BS) {
+    const int v = idx / N, u = idx % N;
+    const bool kept = zz_pos(N, v, u) < r;
+    const bool below_kept = v + 1 < N && zz_pos(N, v + 1, u) < r;
+    if (kept) sh.zz[zz_pos(N, v, u)] = (v * (N + 1) + u) | ((t.cls[v] * 4 + t.cls[u]) << 16);
+    if (kept && !below_kept) sh.cnt[u] = v + 1;
+    if (v == 0 && !kept) sh.cnt[u] = 0;
+  }
 }
 
 // Where this thread's tile lives and where the group's outputs go.
@@ -70,7 +90,7 @@ struct GroupIO {
   int r;                      // retained coefficients per tile
   int32_t* kept;              // [nact][r] block of this group (nullable)
   float* scaled;              // [nact][r] block of this group (nullable)
-  unsigned long long* sse;    // error-energy accumulator of the group's image (nullable)
+  bool sse;                   // compute the error energy
 };
 
 // ------------------------------------------------------------- pixel rows
@@ -174,23 +194,6 @@ __device__ __forceinline__ int quantise(int b, int32_t mq) {
   return b < 0 ? -lev : lev;
 }
 
-// Wave-wide sum, one atomic per wave.
-__device__ __forceinline__ void add_sse(unsigned long long* sse, unsigned long long e) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-  if ((threadIdx.x & 63) == 0 && e != 0) atomicAdd(sse, e);
-}
-
-// Number of rows kept in column u by the zig-zag prefix r (a prefix of the
-// column: rows 0 .. count-1).
-template <int N>
-__device__ __forceinline__ int kept_rows(int u, int r) {
-  int c = 0;
-#pragma unroll
-  for (int v = 0; v < N; ++v) c += zz_pos(N, v, u) < r ? 1 : 0;
-  return c;
-}
-
 template <int N, int BS>
 __device__ __forceinline__ void read_column(const int* S, int j, int k, int (&c)[N]) {
   using C = Cfg<N, BS>;
@@ -218,6 +221,41 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
   for (int e = threadIdx.x; e < count; e += BS) st_stream(dst + e, static_cast<uint32_t>(src[e]));
 }
 
+// Zig-zag outputs of the group: element e = k r + p of the [nact][r] block is
+// coefficient p (zig-zag order) of tile k, read from the padded [k][v][u]
+// layout in S.  Kept values are the coefficients themselves (zonal) or their
+// quantisation levels; scaled values are the coefficients times
+// 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
+template <int N, bool QUANT, int BS>
+__device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh,
+                                               const GroupIO& io) {
+  using C = Cfg<N, BS>;
+  const int r = io.r;
+  const int total = io.nact * r;
+  if (threadIdx.x >= total) return;
+  int k = threadIdx.x / r;
+  int p = threadIdx.x - k * r;
+  const int dk = BS / r, dp = BS - dk * r;
+  for (int e = threadIdx.x; e < total; e += BS) {
+    const int w = sh.zz[p];
+    const int val = S[k * C::TS + (w & 0xffff)];
+    const int ci = w >> 16;
+    if (io.kept != nullptr) {
+      const int b = QUANT ? quantise(val, sh.mq[ci]) : val;
+      st_stream(reinterpret_cast<uint32_t*>(io.kept) + e, static_cast<uint32_t>(b));
+    }
+    if (io.scaled != nullptr)
+      st_stream(reinterpret_cast<uint32_t*>(io.scaled) + e,
+                __builtin_bit_cast(uint32_t, static_cast<float>(val) * sh.s2[ci]));
+    p += dp;
+    k += dk;
+    if (p >= r) {
+      p -= r;
+      ++k;
+    }
+  }
+}
+
 // Row forward: load row i of tile k, transform it, store it transposed so that
 // column j of tile k is contiguous: S[k][j][i].  Returns the raw row in x.
 template <int KIND, int N, int DT, int BS>
@@ -233,14 +271,17 @@ __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, in
 }
 
 // ------------------------------------------------------------ fused group
-// Forward -> retain / quantise -> (outputs) -> inverse -> round -> store -> SSE
-// for the TPW tiles of one workgroup.  Every thread of the workgroup calls it.
+// Forward -> retain / quantise -> (outputs) -> inverse -> round -> store for
+// the TPW tiles of one workgroup; returns this thread's squared
+// reconstruction error (its row of its tile; 0 unless io.sse is set and the
+// tile exists).  Every thread of the workgroup calls it; the tables in sh
+// must have been written before it is called.
 template <int KIND, int N, int DT, bool QUANT, int BS = kBlock>
-__device__ __forceinline__ void compress_group(int* S, const Shared& sh, const GroupIO& io) {
+__device__ __forceinline__ unsigned long long compress_group(int* S, const Shared<N>& sh, const GroupIO& io) {
   using C = Cfg<N, BS>;
+  constexpr RowClasses<N> RC = row_classes<KIND, N>();
   const int a_idx = threadIdx.x / C::TPW;
   const int k = threadIdx.x % C::TPW;
-  const int r = io.r;
 
   // phase 1: rows
   int x[N];
@@ -254,43 +295,35 @@ __device__ __forceinline__ void compress_group(int* S, const Shared& sh, const G
   fwdN<KIND, N>(c);
   if constexpr (DT == DT_U8)
     if (j == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
-  const int keep = kept_rows<N>(j, r);
+  const int keep = sh.cnt[j];
   const int cls_u = sh.cls[j];
+  int mq_u[RC.count], dq_u[RC.count];
+  if constexpr (QUANT) {
+#pragma unroll
+    for (int q = 0; q < RC.count; ++q) {
+      mq_u[q] = sh.mq[q * 4 + cls_u];
+      dq_u[q] = sh.dq[q * 4 + cls_u];
+    }
+  }
   __syncthreads();  // S is free again
 
-  // zig-zag outputs staged per tile as [k][pos] in S
-  if (io.scaled != nullptr) {
-#pragma unroll
-    for (int v = 0; v < N; ++v)
-      if (v < keep) {
-        const float s = sh.s2[sh.cls[v] * 4 + cls_u];
-        S[k * r + zz_pos(N, v, j)] = __builtin_bit_cast(int, static_cast<float>(c[v]) * s);
-      }
+  if (io.kept != nullptr || io.scaled != nullptr) {
+    write_column_rows<N, BS>(S, j, k, c);   // [k][v][u]
     __syncthreads();
-    copy_out<BS>(reinterpret_cast<uint32_t*>(io.scaled), S, io.nact * r);
+    gather_outputs<N, QUANT, BS>(S, sh, io);
     __syncthreads();
   }
+  if (io.dst == nullptr && !io.sse) return 0ull;
+
+  // zonal mask (a prefix of the column), quantise, dequantise
 #pragma unroll
   for (int v = 0; v < N; ++v) {
     int b = v < keep ? c[v] : 0;
-    if constexpr (QUANT) b = quantise(b, sh.mq[sh.cls[v] * 4 + cls_u]);
+    if constexpr (QUANT) b = __mul24(quantise(b, mq_u[RC.cls[v]]), dq_u[RC.cls[v]]);
     c[v] = b;
   }
-  if (io.kept != nullptr) {
-#pragma unroll
-    for (int v = 0; v < N; ++v)
-      if (v < keep) S[k * r + zz_pos(N, v, j)] = c[v];
-    __syncthreads();
-    copy_out<BS>(reinterpret_cast<uint32_t*>(io.kept), S, io.nact * r);
-    __syncthreads();
-  }
-  if (io.dst == nullptr && io.sse == nullptr) return;
 
   // phase 2b: columns, inverse
-  if constexpr (QUANT) {
-#pragma unroll
-    for (int v = 0; v < N; ++v) c[v] = __mul24(c[v], sh.dq[sh.cls[v] * 4 + cls_u]);
-  }
   invN<KIND, N>(c);
   if constexpr (QUANT) {
     // K = 2U: halve exactly so the second pass stays within 32 bits
@@ -308,9 +341,9 @@ __device__ __forceinline__ void compress_group(int* S, const Shared& sh, const G
   // zonal: Z = 4 X, y = round(Z / (4 N^2)); quantised: Z = 2 X~, y = round(X~ / (2 N^2))
   const unsigned long long e = store_row<N, DT, C::SROUND>(
       io.dst, io.tile_pix + static_cast<int64_t>(i) * io.pitch, io.active, z,
-      io.sse != nullptr ? x : nullptr);
-  if (io.sse != nullptr) add_sse(io.sse, io.active ? e : 0ull);
+      io.sse ? x : nullptr);
   __syncthreads();  // S may be reused by the caller
+  return io.active ? e : 0ull;
 }
 
 }  // namespace jam

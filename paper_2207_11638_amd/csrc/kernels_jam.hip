@@ -29,10 +29,12 @@ struct WgPos {
   int64_t pix0;    // pixel offset of the top-left corner of tile k = 0
 };
 
+// Tile group gx (TPW tiles from tile column TPW gx) of tile row blockIdx.y of
+// image blockIdx.z.
 template <int N>
-__device__ __forceinline__ WgPos wg_pos(const Geom& g) {
+__device__ __forceinline__ WgPos wg_pos(const Geom& g, int gx) {
   WgPos w;
-  w.tx0 = blockIdx.x * Cfg<N>::TPW;
+  w.tx0 = gx * Cfg<N>::TPW;
   w.ty = blockIdx.y;
   w.img = blockIdx.z;
   w.tile0 = (static_cast<int64_t>(w.img) * g.tiles_y + w.ty) * g.tiles_x + w.tx0;
@@ -55,25 +57,33 @@ __device__ __forceinline__ GroupIO plain_io(const PassParams& p, const WgPos& w)
   io.r = p.r;
   io.kept = p.cout != nullptr ? p.cout + w.tile0 * p.r : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + w.tile0 * p.r : nullptr;
-  io.sse = p.sse != nullptr ? p.sse + w.img : nullptr;
+  io.sse = p.sse != nullptr;
   return io;
 }
 
+// The workgroup walks p.gpw tile groups along its tile row and adds their
+// error energy to the image's total with one atomic.
 template <int KIND, int N, int DT, bool QUANT>
 __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
   using C = Cfg<N>;
   __shared__ int S[C::WORDS];
-  __shared__ Shared sh;
-  load_tables(sh, p.t, N);
-  const WgPos w = wg_pos<N>(p.g);
-  compress_group<KIND, N, DT, QUANT>(S, sh, plain_io<N>(p, w));
+  __shared__ Shared<N> sh;
+  __shared__ unsigned long long red[kBlock / 64];
+  load_tables<N, kBlock>(sh, p.t, p.r);
+  const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
+  const int g0 = blockIdx.x * p.gpw;
+  const int g1 = min(g0 + p.gpw, groups_x);
+  unsigned long long e = 0;
+  for (int gx = g0; gx < g1; ++gx)
+    e += compress_group<KIND, N, DT, QUANT>(S, sh, plain_io<N>(p, wg_pos<N>(p.g, gx)));
+  if (p.sse != nullptr) block_add_sse<kBlock>(p.sse + blockIdx.z, e, red);
 }
 
 template <int KIND, int N, int DT>
 __global__ __launch_bounds__(kBlock) void forward_jam(PassParams p) {
   using C = Cfg<N>;
   __shared__ int S[C::WORDS];
-  const WgPos w = wg_pos<N>(p.g);
+  const WgPos w = wg_pos<N>(p.g, blockIdx.x);
   const int a_idx = threadIdx.x / C::TPW;
   const int k = threadIdx.x % C::TPW;
   const GroupIO io = plain_io<N>(p, w);
@@ -88,11 +98,14 @@ __global__ __launch_bounds__(kBlock) void forward_jam(PassParams p) {
   if constexpr (DT == DT_U8)
     if (j == 0) c[0] -= 128 * N * N;
   __syncthreads();
-  // natural order within a tile, tiles contiguous: dense staging [k][v][u]
-#pragma unroll
-  for (int v = 0; v < N; ++v) S[k * N * N + v * N + j] = c[v];
+  write_column_rows<N, kBlock>(S, j, k, c);   // padded [k][v][u]
   __syncthreads();
-  copy_out<kBlock>(reinterpret_cast<uint32_t*>(p.cout + w.tile0 * N * N), S, nact * N * N);
+  // natural order within a tile, tiles contiguous in global memory
+  uint32_t* dst = reinterpret_cast<uint32_t*>(p.cout + w.tile0 * N * N);
+  for (int e = threadIdx.x; e < nact * N * N; e += kBlock) {
+    const int kk = e / (N * N), v = (e / N) % N, u = e % N;
+    st_stream(dst + e, static_cast<uint32_t>(S[kk * C::TS + v * C::CS + u]));
+  }
 }
 
 // Inverse from natural-order coefficients (DECOMP = false) or from the
@@ -101,29 +114,51 @@ template <int KIND, int N, int DT, bool QUANT, bool DECOMP>
 __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
   using C = Cfg<N>;
   __shared__ int S[C::WORDS];
-  __shared__ Shared sh;
-  load_tables(sh, p.t, N);
-  const WgPos w = wg_pos<N>(p.g);
+  __shared__ Shared<N> sh;
+  const int r = p.r;
+  load_tables<N, kBlock>(sh, p.t, r);
+  const WgPos w = wg_pos<N>(p.g, blockIdx.x);
   const int a_idx = threadIdx.x / C::TPW;
   const int k = threadIdx.x % C::TPW;
   const bool active = w.tx0 + k < p.g.tiles_x;
   const int nact = min(C::TPW, p.g.tiles_x - w.tx0);
-  const int r = p.r;
-  const int per_tile = DECOMP ? r : N * N;
-  // stage this workgroup's coefficients, contiguous in global memory
-  const int32_t* src = p.cin + w.tile0 * per_tile;
-  for (int e = threadIdx.x; e < nact * per_tile; e += kBlock) S[e] = src[e];
   __syncthreads();
+  // stage this workgroup's coefficients (contiguous in global memory) into the
+  // padded [k][v][u] layout; entries outside the zonal prefix are not read
+  if constexpr (DECOMP) {
+    const int32_t* src = p.cin + w.tile0 * r;
+    if (threadIdx.x < nact * r) {
+      int kk = threadIdx.x / r;
+      int q = threadIdx.x - kk * r;
+      const int dk = kBlock / r, dq = kBlock - dk * r;
+      for (int e = threadIdx.x; e < nact * r; e += kBlock) {
+        S[kk * C::TS + (sh.zz[q] & 0xffff)] = src[e];
+        q += dq;
+        kk += dk;
+        if (q >= r) {
+          q -= r;
+          ++kk;
+        }
+      }
+    }
+  } else {
+    const int32_t* src = p.cin + w.tile0 * N * N;
+    for (int e = threadIdx.x; e < nact * N * N; e += kBlock) {
+      const int kk = e / (N * N), v = (e / N) % N, u = e % N;
+      S[kk * C::TS + v * C::CS + u] = src[e];
+    }
+  }
+  __syncthreads();
+  constexpr RowClasses<N> RC = row_classes<KIND, N>();
   const int j = a_idx;
-  const int keep = kept_rows<N>(j, r);
+  const int keep = active ? sh.cnt[j] : 0;
   const int cls_u = sh.cls[j];
   int c[N];
 #pragma unroll
   for (int v = 0; v < N; ++v) {
-    int b = 0;
-    if (v < keep && active)
-      b = DECOMP ? S[k * r + zz_pos(N, v, j)] : S[k * N * N + v * N + j];
-    if constexpr (QUANT) b = __mul24(b, sh.dq[sh.cls[v] * 4 + cls_u]);
+    int b = S[k * C::TS + v * C::CS + j];
+    b = v < keep ? b : 0;
+    if constexpr (QUANT) b = __mul24(b, sh.dq[RC.cls[v] * 4 + cls_u]);
     c[v] = b;
   }
   __syncthreads();
@@ -144,9 +179,14 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
 
 // ---------------------------------------------------------------- dispatch
 template <int KIND, int N, int DT>
-hipError_t launch_typed(Mode mode, const PassParams& p, hipStream_t s) {
+hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
   using C = Cfg<N>;
-  const dim3 grid((p.g.tiles_x + C::TPW - 1) / C::TPW, p.g.tiles_y, p.g.batch);
+  PassParams p = p_in;
+  const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
+  p.gpw = mode == Mode::Compress
+              ? groups_per_wg(groups_x, static_cast<int64_t>(p.g.tiles_y) * p.g.batch)
+              : 1;
+  const dim3 grid((groups_x + p.gpw - 1) / p.gpw, p.g.tiles_y, p.g.batch);
   const bool quant = p.qstep > 0;
   switch (mode) {
     case Mode::Compress:

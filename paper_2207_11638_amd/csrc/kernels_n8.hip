@@ -24,10 +24,14 @@ using namespace t8;
 // Fused forward -> retain/quantise -> inverse -> round -> store -> SSE.
 // RB is a compile-time bound on r: zig-zag positions >= RB are known to be
 // zero, so the compiler drops the arithmetic that only feeds or reads them.
+// One wave covers 64 tiles (4096 pixels) and adds their error energy to the
+// image's total with one atomic.  (Walking several groups per wave, as the
+// 16/32-point kernels do, makes the compiler keep the tables live across the
+// loop and costs more registers than the atomics it saves.)
 template <int KIND, int DT, int RB, bool QUANT>
 __global__ __launch_bounds__(kWave) void compress8(PassParams p) {
   __shared__ int lds[kWave * row_stride(RB)];
-  const WaveTiles w = wave_tiles(p.g);
+  const WaveTiles w = wave_tiles(p.g, blockIdx.x);
   WaveIO io;
   io.src = p.src;
   io.dst = p.dst;
@@ -39,15 +43,16 @@ __global__ __launch_bounds__(kWave) void compress8(PassParams p) {
   io.r = p.r;
   io.kept = p.cout != nullptr ? p.cout + w.tile0 * p.r : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + w.tile0 * p.r : nullptr;
-  io.sse = p.sse != nullptr ? p.sse + w.img : nullptr;
-  compress_wave<KIND, DT, RB, QUANT, true>(lds, p.t, io);
+  io.sse = p.sse != nullptr;
+  const unsigned long long e = compress_wave<KIND, DT, RB, QUANT, true>(lds, p.t, io);
+  if (p.sse != nullptr) block_add_sse<kWave>(p.sse + w.img, e, nullptr);
 }
 
 template <int KIND, int DT>
 __global__ __launch_bounds__(kWave) void forward8(PassParams p) {
   constexpr int RS = row_stride(kN * kN);
   __shared__ int lds[kWave * RS];
-  const WaveTiles w = wave_tiles(p.g);
+  const WaveTiles w = wave_tiles(p.g, blockIdx.x);
   Raw<DT> raw;
   load_raw<DT>(p.src, w.pix, p.g.pitch, w.active, raw);
   int a[kN][kN];
@@ -79,7 +84,7 @@ template <int KIND, int DT, bool QUANT, bool DECOMP>
 __global__ __launch_bounds__(kWave) void inverse8(PassParams p) {
   constexpr int RS = row_stride(kN * kN);
   __shared__ int lds[kWave * RS];
-  const WaveTiles w = wave_tiles(p.g);
+  const WaveTiles w = wave_tiles(p.g, blockIdx.x);
   const int r = p.r;
   if constexpr (DECOMP) {
     const int32_t* g = p.cin + w.tile0 * r;
@@ -138,7 +143,9 @@ void launch_compress_rb(const PassParams& p, hipStream_t s, dim3 grid) {
 }
 
 template <int KIND, int DT>
-hipError_t launch_typed(Mode mode, const PassParams& p, hipStream_t s) {
+hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
+  PassParams p = p_in;
+  p.gpw = 1;
   const dim3 grid = grid_for(p.g);
   const bool quant = p.qstep > 0;
   switch (mode) {

@@ -195,13 +195,6 @@ __device__ __forceinline__ int table_index(int v, int u) {
   return rc.cls[v] * 4 + rc.cls[u];
 }
 
-// Wave-wide sum, one atomic per wave.
-__device__ __forceinline__ void add_sse(unsigned long long* sse, unsigned long long e) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0 && e != 0) atomicAdd(sse, e);
-}
-
 // Where this thread's tile lives and where its wave's outputs go.
 struct WaveIO {
   const void* src;
@@ -214,7 +207,7 @@ struct WaveIO {
   int r;                      // retained coefficients per tile
   int32_t* kept;              // [nact][r] block of this wave (nullable)
   float* scaled;              // [nact][r] block of this wave (nullable)
-  unsigned long long* sse;    // accumulator of the wave's image (nullable)
+  bool sse;                   // compute the error energy
 };
 
 struct WaveTiles {
@@ -225,10 +218,12 @@ struct WaveTiles {
   int64_t pix;     // pixel offset of this thread's tile
 };
 
-__device__ __forceinline__ WaveTiles wave_tiles(const Geom& g) {
+// Tiles of group gx (64 tiles from tile column 64 gx) of tile row blockIdx.y
+// of image blockIdx.z.
+__device__ __forceinline__ WaveTiles wave_tiles(const Geom& g, int gx) {
   WaveTiles w;
   w.lane = threadIdx.x;
-  const int tx0 = blockIdx.x * kWave;
+  const int tx0 = gx * kWave;
   w.tx = tx0 + w.lane;
   w.img = blockIdx.z;
   w.nact = min(kWave, g.tiles_x - tx0);
@@ -294,17 +289,19 @@ __device__ __forceinline__ void copy_tiles_in_rt(int* lds, const int32_t* g, int
 
 
 // ------------------------------------------------------------- fused wave
-// Forward -> retain/quantise -> (outputs) -> inverse -> round -> store -> SSE
-// of the wave's tiles.  RB is a compile-time bound on r: zig-zag positions
-// >= RB are known to be zero, so the compiler drops the arithmetic that only
-// feeds or reads them.  With STAGED the [tile][r] outputs go through ``lds``
-// (64 * row_stride(RB) words owned by this wave) for coalesced stores;
-// otherwise each thread stores its own r words.  Every thread of the
-// workgroup must call this (it synchronises with __syncthreads when STAGED).
+// Forward -> retain/quantise -> (outputs) -> inverse -> round -> store of the
+// wave's tiles; returns this thread's squared reconstruction error (0 unless
+// io.sse is set and the tile exists).  RB is a compile-time bound on r:
+// zig-zag positions >= RB are known to be zero, so the compiler drops the
+// arithmetic that only feeds or reads them.  With STAGED the [tile][r]
+// outputs go through ``lds`` (64 * row_stride(RB) words owned by this wave)
+// for coalesced stores; otherwise each thread stores its own r words.  Every
+// thread of the workgroup must call this (it synchronises with
+// __syncthreads when STAGED).
 // TAB is the type of the constant tables (a Tables in kernel-argument or
 // constant memory, read with scalar loads).
 template <int KIND, int DT, int RB, bool QUANT, bool STAGED, typename TAB>
-__device__ __forceinline__ void compress_wave(int* lds, const TAB& t, const WaveIO& io) {
+__device__ __forceinline__ unsigned long long compress_wave(int* lds, const TAB& t, const WaveIO& io) {
   constexpr int RS = row_stride(RB);
   Raw<DT> raw;
   load_raw<DT>(io.src, io.tile_pix, io.pitch, io.active, raw);
@@ -369,7 +366,7 @@ __device__ __forceinline__ void compress_wave(int* lds, const TAB& t, const Wave
         if (k < r) io.kept[lane * r + k] = a[kZZ.v[k]][kZZ.u[k]];
     }
   }
-  if (io.dst == nullptr && io.sse == nullptr) return;
+  if (io.dst == nullptr && !io.sse) return 0ull;
   if constexpr (QUANT) {
 #pragma unroll
     for (int v = 0; v < kN; ++v)
@@ -383,7 +380,7 @@ __device__ __forceinline__ void compress_wave(int* lds, const TAB& t, const Wave
   Raw<DT> rec;
   round_pack<DT, S>(a, rec);
   if (io.dst != nullptr && io.active) store_raw<DT>(io.dst, io.tile_pix, io.pitch, rec);
-  if (io.sse != nullptr) add_sse(io.sse, io.active ? tile_sse<DT>(raw, rec) : 0ull);
+  return io.sse && io.active ? tile_sse<DT>(raw, rec) : 0ull;
 }
 
 }  // namespace t8
