@@ -107,7 +107,7 @@ __global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
   io.kept = p.kept != nullptr ? p.kept + kb : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + kb : nullptr;
   io.sse = p.sse != nullptr;
-  const unsigned long long e = t8::compress_wave<KIND, DT, RB, QUANT, STAGED>(
+  const unsigned long long e = t8::compress_wave<KIND, DT, RB, QUANT, STAGED, false>(
       S + (STAGED ? w * kWave * t8::row_stride(RB) : 0), p.t, io);
   if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
 }
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
   io.kept = p.kept != nullptr ? p.kept + it.kept_base : nullptr;
   io.scaled = p.scaled != nullptr ? p.scaled + it.kept_base : nullptr;
   io.sse = p.sse != nullptr;
-  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS>(S, sh, io);
+  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false>(S, sh, io);
   if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
 }
 

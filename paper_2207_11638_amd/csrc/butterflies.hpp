@@ -254,6 +254,15 @@ __device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
   __builtin_nontemporal_store(v.z, &p->z);
   __builtin_nontemporal_store(v.w, &p->w);
 }
+
+// Non-temporal store when NT (whole lines written by one wave: the data is
+// not read again), ordinary store otherwise (a row segment that shares its
+// lines with tiles that another launch writes: the cache merges them).
+template <bool NT, typename T>
+__device__ __forceinline__ void st_pix(T* p, T v) {
+  if constexpr (NT) st_stream(p, v);
+  else *p = v;
+}
 #endif
 
 }  // namespace adct

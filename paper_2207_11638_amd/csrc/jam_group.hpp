@@ -128,7 +128,7 @@ __device__ __forceinline__ void load_row(const void* src, int64_t off, bool acti
 
 // Round z / 2^S half away from zero, clip, store one row; return its squared
 // error against the original row x (when x is given).
-template <int N, int DT, int S>
+template <int N, int DT, int S, bool NT = true>
 __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, bool active,
                                                         const int (&z)[N], const int* x) {
   int y[N];
@@ -168,7 +168,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
           const int* yy = y + 16 * q + 4 * d;
           ws[d] = yy[0] | (yy[1] << 8) | (yy[2] << 16) | (yy[3] << 24);
         }
-        st_stream(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        st_pix<NT>(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
       }
     } else {
       uint4* p = reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off);
@@ -180,7 +180,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
           const int* yy = y + 8 * q + 2 * d;
           ws[d] = (yy[0] & 0xffff) | (static_cast<uint32_t>(yy[1]) << 16);
         }
-        st_stream(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
+        st_pix<NT>(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
       }
     }
   }
@@ -275,8 +275,9 @@ __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, in
 // the TPW tiles of one workgroup; returns this thread's squared
 // reconstruction error (its row of its tile; 0 unless io.sse is set and the
 // tile exists).  Every thread of the workgroup calls it; the tables in sh
-// must have been written before it is called.
-template <int KIND, int N, int DT, bool QUANT, int BS = kBlock>
+// must have been written before it is called.  NT selects non-temporal
+// reconstruction stores.
+template <int KIND, int N, int DT, bool QUANT, int BS = kBlock, bool NT = true>
 __device__ __forceinline__ unsigned long long compress_group(int* S, const Shared<N>& sh, const GroupIO& io) {
   using C = Cfg<N, BS>;
   constexpr RowClasses<N> RC = row_classes<KIND, N>();
@@ -339,7 +340,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   read_row<N, BS>(S, i, k, z);
   invN<KIND, N>(z);
   // zonal: Z = 4 X, y = round(Z / (4 N^2)); quantised: Z = 2 X~, y = round(X~ / (2 N^2))
-  const unsigned long long e = store_row<N, DT, C::SROUND>(
+  const unsigned long long e = store_row<N, DT, C::SROUND, NT>(
       io.dst, io.tile_pix + static_cast<int64_t>(i) * io.pitch, io.active, z,
       io.sse ? x : nullptr);
   __syncthreads();  // S may be reused by the caller

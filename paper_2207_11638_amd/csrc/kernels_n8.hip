@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kWave) void inverse8(PassParams p) {
   constexpr int S = QUANT ? 9 : 8;
   Raw<DT> rec;
   round_pack<DT, S>(a, rec);
-  if (w.active) store_raw<DT>(p.dst, w.pix, p.g.pitch, rec);
+  if (w.active) store_raw<DT, true>(p.dst, w.pix, p.g.pitch, rec);
 }
 
 // ---------------------------------------------------------------- dispatch

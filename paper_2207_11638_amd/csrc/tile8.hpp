@@ -105,15 +105,15 @@ __device__ __forceinline__ void round_pack(const int (&z)[kN][kN], Raw<DT>& out)
   }
 }
 
-template <int DT>
+template <int DT, bool NT>
 __device__ __forceinline__ void store_raw(void* dst, int64_t off, int64_t pitch, const Raw<DT>& raw) {
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
     if constexpr (DT == DT_U8)
-      st_stream(reinterpret_cast<uint2*>(static_cast<uint8_t*>(dst) + off + i * pitch),
+      st_pix<NT>(reinterpret_cast<uint2*>(static_cast<uint8_t*>(dst) + off + i * pitch),
                 make_uint2(raw.w[i][0], raw.w[i][1]));
     else
-      st_stream(reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off + i * pitch),
+      st_pix<NT>(reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off + i * pitch),
                 make_uint4(raw.w[i][0], raw.w[i][1], raw.w[i][2], raw.w[i][3]));
   }
 }
@@ -297,10 +297,10 @@ __device__ __forceinline__ void copy_tiles_in_rt(int* lds, const int32_t* g, int
 // outputs go through ``lds`` (64 * row_stride(RB) words owned by this wave)
 // for coalesced stores; otherwise each thread stores its own r words.  Every
 // thread of the workgroup must call this (it synchronises with
-// __syncthreads when STAGED).
+// __syncthreads when STAGED).  NT selects non-temporal reconstruction stores.
 // TAB is the type of the constant tables (a Tables in kernel-argument or
 // constant memory, read with scalar loads).
-template <int KIND, int DT, int RB, bool QUANT, bool STAGED, typename TAB>
+template <int KIND, int DT, int RB, bool QUANT, bool STAGED, bool NT = true, typename TAB>
 __device__ __forceinline__ unsigned long long compress_wave(int* lds, const TAB& t, const WaveIO& io) {
   constexpr int RS = row_stride(RB);
   Raw<DT> raw;
@@ -379,7 +379,7 @@ __device__ __forceinline__ unsigned long long compress_wave(int* lds, const TAB&
   constexpr int S = QUANT ? 9 : 8;
   Raw<DT> rec;
   round_pack<DT, S>(a, rec);
-  if (io.dst != nullptr && io.active) store_raw<DT>(io.dst, io.tile_pix, io.pitch, rec);
+  if (io.dst != nullptr && io.active) store_raw<DT, NT>(io.dst, io.tile_pix, io.pitch, rec);
   return io.sse && io.active ? tile_sse<DT>(raw, rec) : 0ull;
 }
 
