@@ -226,6 +226,105 @@ ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst,
  * 8, 16 and 32, buckets, compute units of the device. */
 ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
 
+/* ----------------------------------------------------------------------
+ * Serving: continuous batching of independent compress requests.
+ *
+ * Each request is one image compressed with the fused pipeline of
+ * adct_compress (its own transform, n, r, qstep and dtype).  A server admits
+ * requests against an HBM budget, queues them, and launches whatever is
+ * queued as one batch whenever one of its max_inflight batch slots is free:
+ * one launch per (transform, n, dtype, quantiser, r class) covering every
+ * request of that class in the batch.  Requests that arrive while batches
+ * run join the next batch, so the batch size follows the load.
+ *
+ * Memory.  The server owns a device arena of budget_bytes for the outputs
+ * (reconstruction with the request's pitch, retained coefficients, optional
+ * scaled coefficients), allocated at the first flush.  A request is charged
+ * its input plus its outputs; adct_server_submit returns ADCT_E_BUDGET when
+ * the charge does not fit next to the requests in flight (retry after a
+ * poll), or when it exceeds the whole budget.  Batches complete in
+ * submission order, so the arena is a ring.
+ *
+ * Time.  done_ms and adct_server_clock_ms use one clock: milliseconds of the
+ * host's steady clock since the server was created.  A batch's completion
+ * time is read from a HIP event recorded after its last operation, aligned
+ * to the host clock once at the first flush.
+ *
+ * A server is not thread-safe: one host thread drives it.
+ * ---------------------------------------------------------------------- */
+
+typedef struct adct_server adct_server_t;
+
+typedef struct {
+  const void* d_src;   /* device pixels, valid until the request completes       */
+  void* h_kept;        /* NULL, or host memory receiving the tiles*r kept words  */
+  void* h_scaled;      /* NULL, or host memory receiving tiles*r scaled floats   */
+  void* h_recon;       /* NULL, or host memory receiving height*pitch pixels     */
+  int64_t pitch;       /* pixels between rows, >= width                         */
+  int64_t tag;         /* caller's identifier, echoed in the completion          */
+  int32_t transform;   /* ADCT_T1 or ADCT_T2                                     */
+  int32_t n;           /* 8, 16 or 32                                            */
+  int32_t r;           /* 1 <= r <= n*n                                          */
+  int32_t qstep;       /* 0 (zonal) or 1..4096                                   */
+  int32_t dtype;       /* ADCT_U8 or ADCT_I16                                    */
+  int32_t height;      /* multiple of n                                          */
+  int32_t width;       /* multiple of n                                          */
+  int32_t want_scaled; /* nonzero: also compute the float32 scaled coefficients  */
+                       /* (h_scaled needs want_scaled)                           */
+} adct_request_t;
+
+typedef struct {
+  int64_t tag;             /* the request's tag                                  */
+  int64_t batch;           /* sequence number of the batch it ran in (0, 1, ...) */
+  uint64_t sse;            /* error energy of its reconstruction                 */
+  double done_ms;          /* completion time on the server clock                */
+  const int32_t* d_kept;   /* outputs in the arena, valid until the next poll:   */
+  const float* d_scaled;   /*   kept [tiles][r] (zig-zag order), scaled (or NULL), */
+  const void* d_recon;     /*   reconstruction (height rows of pitch pixels)     */
+} adct_completion_t;
+
+/* Create a server (host state only; no HIP call).  budget_bytes > 0,
+ * 1 <= max_inflight <= 8 batch slots, 1 <= max_batch <= 4096 requests per
+ * batch; work is enqueued on stream. */
+ADCT_API int adct_server_create(int64_t budget_bytes, int max_inflight, int max_batch,
+                                adct_stream_t stream, adct_server_t** server);
+
+/* Wait for every launched batch, then free the server and its arena. */
+ADCT_API int adct_server_destroy(adct_server_t* server);
+
+/* Validate and admit one request (host only).  ADCT_OK: queued.
+ * ADCT_E_BUDGET: not admitted now (or never, if it exceeds the budget). */
+ADCT_API int adct_server_submit(adct_server_t* server, const adct_request_t* request);
+
+/* Launch the queued requests (at most max_batch, oldest first) as one batch
+ * if a batch slot is free; *launched receives the number of requests
+ * launched (0 when nothing is queued or every slot is busy). */
+ADCT_API int adct_server_flush(adct_server_t* server, int* launched);
+
+/* Report completed batches, oldest first, as long as their requests fit in
+ * out[0 .. max_out) (max_out must be at least max_batch).  wait != 0 blocks
+ * until every launched batch has completed.  Arena space of the batches
+ * reported by the previous poll is released first. */
+ADCT_API int adct_server_poll(adct_server_t* server, int wait, adct_completion_t* out,
+                              int max_out, int* n_out);
+
+/* out[0..7] = submitted, completed, batches launched, queued, in flight,
+ * bytes charged, largest batch, ADCT_E_BUDGET refusals. */
+ADCT_API int adct_server_stats(const adct_server_t* server, int64_t* out);
+
+/* Milliseconds on the server clock. */
+ADCT_API double adct_server_clock_ms(const adct_server_t* server);
+
+/* Replay an arrival trace in real time on the calling thread: request i
+ * arrives arrival_ms[i] milliseconds after the start (non-decreasing), is
+ * admitted in arrival order (waiting while the budget is full), batched and
+ * launched; the call returns when every request has completed.
+ * latency_ms[i] = completion - arrival, batch_of[i] = its batch (either may be
+ * NULL).  A request that fails validation gets latency NaN and batch -1. */
+ADCT_API int adct_server_run_trace(adct_server_t* server, const adct_request_t* requests,
+                                   const double* arrival_ms, int64_t n, double* latency_ms,
+                                   int64_t* batch_of);
+
 #ifdef __cplusplus
 }
 #endif

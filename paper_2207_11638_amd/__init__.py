@@ -248,3 +248,107 @@ class BatchPlan:
         _lib.check(_lib.load().adct_batch_run(self._h, _ptr(src), _ptr(dst), _ptr(kept),
                                               _ptr(scaled), _ptr(sse), _ptr(psnr),
                                               _RUN_MODES[mode], _stream_handle(src.device)))
+
+
+# ----------------------------------------------------------------- serving
+# numpy mirrors of adct_request_t and adct_completion_t
+REQUEST = np.dtype([("d_src", np.uint64), ("h_kept", np.uint64), ("h_scaled", np.uint64),
+                    ("h_recon", np.uint64),
+                    ("pitch", np.int64), ("tag", np.int64), ("transform", np.int32),
+                    ("n", np.int32), ("r", np.int32), ("qstep", np.int32), ("dtype", np.int32),
+                    ("height", np.int32), ("width", np.int32), ("want_scaled", np.int32)])
+COMPLETION = np.dtype([("tag", np.int64), ("batch", np.int64), ("sse", np.uint64),
+                       ("done_ms", np.float64), ("d_kept", np.uint64), ("d_scaled", np.uint64),
+                       ("d_recon", np.uint64)])
+
+
+def request(x, transform: int, n: int, r: int, qstep: int = 0, tag: int = 0,
+            want_scaled: bool = False, h_kept=None, h_scaled=None, h_recon=None):
+    """One REQUEST record for the 2D image tensor x (uint8 or int16 on the
+    GPU, rows contiguous).  h_kept / h_scaled / h_recon: optional host
+    tensors (pinned for an asynchronous copy) that receive the kept
+    coefficients ([H/n * W/n * r] int32), the scaled coefficients (float32,
+    needs want_scaled) and the reconstruction (x's rows, x's pitch)."""
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("x must be a 2D tensor with contiguous rows")
+    rec = np.zeros((), dtype=REQUEST)
+    rec["d_src"] = x.data_ptr()
+    rec["h_kept"] = 0 if h_kept is None else h_kept.data_ptr()
+    rec["h_scaled"] = 0 if h_scaled is None else h_scaled.data_ptr()
+    rec["h_recon"] = 0 if h_recon is None else h_recon.data_ptr()
+    rec["pitch"] = x.stride(0)
+    rec["tag"] = tag
+    rec["transform"], rec["n"], rec["r"], rec["qstep"] = transform, n, r, qstep
+    rec["dtype"] = _dtype_code(x)
+    rec["height"], rec["width"] = x.shape
+    rec["want_scaled"] = int(bool(want_scaled))
+    return rec
+
+
+class Server:
+    """Continuous-batching compress server on one GPU stream (see the
+    adct_server_* calls).  budget: HBM bytes charged by the requests in
+    flight (inputs + outputs); max_inflight batch slots; max_batch requests
+    per batch."""
+
+    def __init__(self, budget: int, max_inflight: int = 2, max_batch: int = 1024, stream=None):
+        handle = C.c_void_p()
+        self.max_batch = max_batch
+        _lib.check(_lib.load().adct_server_create(int(budget), max_inflight, max_batch,
+                                                  stream, C.byref(handle)))
+        self._h = handle
+        self._out = np.zeros(max_batch, dtype=COMPLETION)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().adct_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, rec) -> bool:
+        """Queue one request; False when the budget cannot take it now."""
+        rec = np.ascontiguousarray(rec, dtype=REQUEST)
+        st = _lib.load().adct_server_submit(self._h, rec.ctypes.data)
+        if st == -5:
+            return False
+        _lib.check(st)
+        return True
+
+    def flush(self) -> int:
+        launched = C.c_int(0)
+        _lib.check(_lib.load().adct_server_flush(self._h, C.byref(launched)))
+        return launched.value
+
+    def poll(self, wait: bool = False):
+        """Completed requests (structured COMPLETION array), oldest first."""
+        n = C.c_int(0)
+        _lib.check(_lib.load().adct_server_poll(self._h, int(wait), self._out.ctypes.data,
+                                                len(self._out), C.byref(n)))
+        return self._out[: n.value].copy()
+
+    def stats(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _lib.check(_lib.load().adct_server_stats(self._h, out.ctypes.data))
+        keys = ("submitted", "completed", "batches", "queued", "in_flight", "charged",
+                "max_batch", "refused")
+        return dict(zip(keys, out.tolist()))
+
+    def clock_ms(self) -> float:
+        return float(_lib.load().adct_server_clock_ms(self._h))
+
+    def run_trace(self, requests, arrival_ms):
+        """Replay an arrival trace in real time (native loop); returns
+        (latency_ms, batch_of) arrays."""
+        reqs = np.ascontiguousarray(requests, dtype=REQUEST)
+        arr = np.ascontiguousarray(arrival_ms, dtype=np.float64)
+        lat = np.zeros(len(reqs), dtype=np.float64)
+        bat = np.zeros(len(reqs), dtype=np.int64)
+        _lib.check(_lib.load().adct_server_run_trace(self._h, reqs.ctypes.data, arr.ctypes.data,
+                                                     len(reqs), lat.ctypes.data,
+                                                     bat.ctypes.data))
+        return lat, bat

@@ -35,6 +35,14 @@ _SIGNATURES = {
     "adct_batch_set_shape": ([_vp, _i32, _i32], _i32),
     "adct_batch_tune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "adct_batch_info": ([_vp, _vp], _i32),
+    "adct_server_create": ([_i64, _i32, _i32, _vp, _vp], _i32),
+    "adct_server_destroy": ([_vp], _i32),
+    "adct_server_submit": ([_vp, _vp], _i32),
+    "adct_server_flush": ([_vp, _vp], _i32),
+    "adct_server_poll": ([_vp, _i32, _vp, _i32, _vp], _i32),
+    "adct_server_stats": ([_vp, _vp], _i32),
+    "adct_server_clock_ms": ([_vp], C.c_double),
+    "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp], _i32),
 }
 
 ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE = 0, 1, 2

@@ -1,0 +1,146 @@
+"""Host-side behaviour of the serving engine: argument checks, admission
+against the HBM budget and the arena ring.  No GPU is touched: a server
+only allocates device memory at its first flush."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2207_11638_amd as adct
+from paper_2207_11638_amd import _lib
+
+E_ARG, E_SHAPE, E_ALIGN, E_BUDGET = -1, -2, -3, -5
+FAKE_DEVICE_PTR = 1 << 20      # never dereferenced by submit
+
+
+def _lib_or_skip():
+    try:
+        return _lib.load()
+    except RuntimeError as e:  # pragma: no cover - library not built
+        pytest.skip(str(e))
+
+
+def req(h=64, w=64, n=8, r=10, q=0, dtype=adct.ADCT_U8, pitch=None, scaled=False, ptr=None):
+    rec = np.zeros((), dtype=adct.REQUEST)
+    rec["d_src"] = FAKE_DEVICE_PTR if ptr is None else ptr
+    rec["pitch"] = w if pitch is None else pitch
+    rec["transform"], rec["n"], rec["r"], rec["qstep"], rec["dtype"] = 1, n, r, q, dtype
+    rec["height"], rec["width"] = h, w
+    rec["want_scaled"] = int(scaled)
+    return rec
+
+
+def charge(h, w, n, r, esize=1, scaled=False, pitch=None):
+    """Budget charge of one request: input + reconstruction + coefficient
+    outputs, each output block rounded up to 256 bytes."""
+    pitch = pitch or w
+    a = lambda x: (x + 255) // 256 * 256
+    tiles = (h // n) * (w // n)
+    image = h * pitch * esize
+    return image + a(image) + a(tiles * r * 4) + (a(tiles * r * 4) if scaled else 0)
+
+
+def status(srv, rec):
+    return _lib.load().adct_server_submit(srv._h, np.ascontiguousarray(rec).ctypes.data)
+
+
+def test_create_argument_checks():
+    lib = _lib_or_skip()
+    import ctypes as C
+    h = C.c_void_p()
+    assert lib.adct_server_create(0, 2, 16, None, C.byref(h)) == E_ARG
+    assert lib.adct_server_create(1 << 20, 0, 16, None, C.byref(h)) == E_ARG
+    assert lib.adct_server_create(1 << 20, 9, 16, None, C.byref(h)) == E_ARG
+    assert lib.adct_server_create(1 << 20, 2, 0, None, C.byref(h)) == E_ARG
+    assert lib.adct_server_create(1 << 20, 2, 4097, None, C.byref(h)) == E_ARG
+    assert lib.adct_server_create(1 << 20, 2, 16, None, None) == E_ARG
+
+
+def test_submit_validation():
+    _lib_or_skip()
+    srv = adct.Server(1 << 24, max_inflight=2, max_batch=16)
+    assert status(srv, req(n=12)) == E_ARG
+    assert status(srv, req(r=65)) == E_ARG
+    assert status(srv, req(r=0)) == E_ARG
+    assert status(srv, req(q=5000)) == E_ARG
+    assert status(srv, req(dtype=7)) == E_ARG
+    assert status(srv, req(h=60)) == E_SHAPE
+    assert status(srv, req(w=64, pitch=32)) == E_SHAPE
+    assert status(srv, req(n=16, h=64, w=72)) == E_SHAPE
+    assert status(srv, req(ptr=FAKE_DEVICE_PTR + 4)) == E_ALIGN
+    assert status(srv, req(ptr=0)) == E_ARG
+    bad = req(scaled=False)
+    bad["h_scaled"] = 1 << 21
+    assert status(srv, bad) == E_ARG
+    assert srv.stats()["submitted"] == 0
+    srv.close()
+
+
+def test_admission_charges_input_and_outputs():
+    _lib_or_skip()
+    c = charge(64, 64, 8, 10)
+    srv = adct.Server(2 * c + c // 2, max_inflight=2, max_batch=16)
+    assert srv.submit(req())
+    assert srv.submit(req())
+    assert srv.stats()["charged"] == 2 * c
+    assert not srv.submit(req())          # a third does not fit now
+    st = srv.stats()
+    assert st["submitted"] == 2 and st["queued"] == 2 and st["refused"] == 1
+    srv.close()
+
+
+def test_request_larger_than_budget_is_refused():
+    _lib_or_skip()
+    srv = adct.Server(charge(64, 64, 8, 10) - 1, max_inflight=1, max_batch=4)
+    assert status(srv, req()) == E_BUDGET
+    assert "whole budget" in _lib.load().adct_last_error().decode()
+    srv.close()
+
+
+def test_charge_counts_pitch_scaled_and_int16():
+    _lib_or_skip()
+    for kw, c in [(dict(pitch=128), charge(64, 64, 8, 10, pitch=128)),
+                  (dict(scaled=True), charge(64, 64, 8, 10, scaled=True)),
+                  (dict(dtype=adct.ADCT_I16), charge(64, 64, 8, 10, esize=2)),
+                  (dict(n=32, r=100), charge(64, 64, 32, 100))]:
+        srv = adct.Server(1 << 24, max_inflight=1, max_batch=4)
+        assert srv.submit(req(**kw))
+        assert srv.stats()["charged"] == c
+        srv.close()
+
+
+def test_poll_needs_room_for_a_batch():
+    lib = _lib_or_skip()
+    import ctypes as C
+    srv = adct.Server(1 << 20, max_inflight=1, max_batch=8)
+    out = np.zeros(4, dtype=adct.COMPLETION)
+    n = C.c_int(0)
+    assert lib.adct_server_poll(srv._h, 0, out.ctypes.data, 4, C.byref(n)) == E_ARG
+    srv.close()
+
+
+def test_trace_arguments():
+    lib = _lib_or_skip()
+    srv = adct.Server(1 << 20, max_inflight=1, max_batch=8)
+    reqs = np.stack([req(), req()])
+    with pytest.raises(adct.AdctError):
+        srv.run_trace(reqs, np.array([1.0, 0.5]))      # decreasing arrivals
+    lat, bat = srv.run_trace(reqs[:0], np.zeros(0))    # empty trace: no device work
+    assert len(lat) == 0 and len(bat) == 0
+    srv.close()
+
+
+def test_clock_is_monotonic():
+    _lib_or_skip()
+    srv = adct.Server(1 << 20)
+    a = srv.clock_ms()
+    b = srv.clock_ms()
+    assert 0.0 <= a <= b and math.isfinite(b)
+    srv.close()
+
+
+def test_request_record_layout():
+    # the numpy mirrors must match the C structs field for field
+    assert adct.REQUEST.itemsize == 80
+    assert adct.COMPLETION.itemsize == 56
+    assert list(adct.REQUEST.names[:5]) == ["d_src", "h_kept", "h_scaled", "h_recon", "pitch"]
