@@ -153,9 +153,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("c1", "c3", "plain"), default="c1",
+    ap.add_argument("--workload", choices=("c1", "c3", "c4", "plain"), default="c1",
                     help="c1: the 1024 x 2048^2 sweep (default); c3: the ragged batch; "
+                         "c4: the serving loop; "
                          "plain: one fused configuration (--n, --transform, --r, --qstep)")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c4: arrivals per second")
+    ap.add_argument("--duration", type=float, default=30.0, help="c4: trace length (s)")
+    ap.add_argument("--pool", type=int, default=64, help="c4: device-resident images")
+    ap.add_argument("--check-max", type=int, default=300,
+                    help="c4: at most this many sampled requests checked against the oracle")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="c4: HBM admission budget")
+    ap.add_argument("--sweep", type=str, default="8000,32000,128000,512000,1000000",
+                    help="c4: further arrival rates (1 s traces each), '' for none")
     ap.add_argument("--n", type=int, default=8)
     ap.add_argument("--transform", type=int, default=2)
     ap.add_argument("--r", type=int, default=10)
@@ -181,6 +190,8 @@ def main():
 
     if args.workload == "c3":
         run_c3(args)
+    elif args.workload == "c4":
+        run_c4(args)
     elif args.workload == "plain":
         run_plain(args)
     else:
@@ -524,6 +535,168 @@ def run_c3(args):
                      "kernel": "bucket8 / bucket_jam (one launch per bucket)"},
         "plan": info,
         "tuned_block_sizes": chosen.tolist(),
+        "parity_sample": check,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+
+# -------------------------------------------------------------------- serving
+def _c4_check(task):
+    """Oracle check of one served request (worker process)."""
+    import numpy as np
+
+    from oracle import pipeline as P
+    img, kind, n, r, kept, recon, sse = task
+    want = P.compress(img, kind, n, r)
+    return (np.array_equal(kept.reshape(want["kept"].shape), want["kept"])
+            and np.array_equal(recon, want["recon"]) and int(sse) == want["sse"])
+
+
+def run_c4(args):
+    """Serving loop: Poisson arrivals at --rate requests/s for --duration s
+    (seed 4000); each request is one image from a pool of --pool
+    device-resident AR(1) images (sides log-normal around 1024 in [64, 4096],
+    multiples of 32) with its own T in {T1, T2}, N in {8, 16, 32} and
+    r in 6..28, compressed with kept int32 + recon + error energy.  The trace
+    is replayed in real time by the library's native loop (admission by a
+    32 GB budget, continuous batching over two batch slots).  Reports p50/p99
+    latency (arrival to completion event) and served Gpixel/s, checks a
+    sample of >= 1 % of the requests (at most --check-max) against the oracle,
+    and sweeps higher arrival rates towards saturation."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    import paper_2207_11638_amd as adct
+    import synth
+
+    dev = torch.device("cuda:0")
+    n_req = int(args.rate * args.duration)
+    trace = synth.serving_requests(n_req, seed=4000, rate_hz=args.rate)
+    pool_n = min(args.pool, n_req)
+    sizes = np.array([(t["h"], t["w"]) for t in trace[:pool_n]], dtype=np.int64)
+    px = sizes[:, 0] * sizes[:, 1]
+    offsets = np.concatenate([[0], np.cumsum(px)[:-1]])
+    seeds = [5000 + i for i in range(pool_n)]
+    rhos = [0.85 + 0.13 * ((i * 0.618) % 1.0) for i in range(pool_n)]
+    t0 = time.perf_counter()
+    arena = synth.ar1_arena(offsets, sizes[:, 0], sizes[:, 1], sizes[:, 1], seeds, rhos,
+                            int(px.sum()), workers=args.gen_workers)
+    log(f"pool of {pool_n} images ({px.sum() / 1e6:.1f} Mpx) generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    d_arena = torch.from_numpy(arena).to(dev)
+    pool = [d_arena[int(o):int(o) + int(p)].view(int(h), int(w))
+            for o, p, (h, w) in zip(offsets, px, sizes)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream().cuda_stream
+    budget = int(args.budget_gb * (1 << 30))
+
+    pool_ptr = np.array([int(x.data_ptr()) for x in pool], dtype=np.uint64)
+
+    def build(trace_, sample_every):
+        m = len(trace_)
+        j = np.arange(m) % pool_n
+        recs = np.zeros(m, dtype=adct.REQUEST)
+        recs["d_src"] = pool_ptr[j]
+        recs["pitch"] = sizes[j, 1]
+        recs["tag"] = np.arange(m)
+        recs["transform"] = [t["transform"] for t in trace_]
+        recs["n"] = [t["n"] for t in trace_]
+        recs["r"] = [t["r"] for t in trace_]
+        recs["dtype"] = adct.ADCT_U8
+        recs["height"] = sizes[j, 0]
+        recs["width"] = sizes[j, 1]
+        checks = []
+        for i in range(0, m, sample_every) if sample_every else ():
+            t = trace_[i]
+            h, w = (int(v) for v in sizes[j[i]])
+            h_kept = torch.empty((h // t["n"]) * (w // t["n"]) * t["r"],
+                                 dtype=torch.int32).pin_memory()
+            h_recon = torch.empty((h, w), dtype=torch.uint8).pin_memory()
+            recs["h_kept"][i] = h_kept.data_ptr()
+            recs["h_recon"][i] = h_recon.data_ptr()
+            checks.append((i, int(j[i]), h_kept, h_recon))
+        return recs, checks
+
+    def replay(trace_, rate, sample_every=0):
+        recs, checks = build(trace_, sample_every)
+        arrival_ms = np.array([t["t"] for t in trace_]) * 1e3
+        srv = adct.Server(budget, max_inflight=2, max_batch=1024, stream=stream)
+        lat, batch, sse = srv.run_trace(recs, arrival_ms)
+        st = srv.stats()
+        srv.close()
+        served_px = int(px[np.arange(len(trace_)) % pool_n].sum())
+        span_s = (np.max(arrival_ms + lat) - arrival_ms[0]) / 1e3
+        res = {"rate_hz": rate, "requests": len(trace_),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "max_ms": round(float(np.max(lat)), 3),
+               "served_gpixel_s": round(served_px / span_s / 1e9, 3),
+               "offered_gpixel_s": round(served_px / (arrival_ms[-1] / 1e3) / 1e9, 3),
+               "batches": int(st["batches"]), "largest_batch": int(st["max_batch"]),
+               "mean_batch": round(len(trace_) / max(1, st["batches"]), 2),
+               "budget_waits": int(st["refused"])}
+        return res, checks, sse
+
+    main_res, checks, sse = replay(trace, args.rate,
+                                   sample_every=max(1, min(100, n_req // max(1, args.check_max))))
+    log(f"served {n_req} requests at {args.rate:.0f}/s: p50 {main_res['p50_ms']} ms, "
+        f"p99 {main_res['p99_ms']} ms, {main_res['served_gpixel_s']} Gpx/s, "
+        f"{main_res['batches']} batches")
+
+    check = None
+    if not args.no_check:
+        tasks = []
+        for i, j, hk, hr in checks:
+            t = trace[i]
+            img = arena[int(offsets[j]):int(offsets[j] + px[j])].reshape(int(sizes[j, 0]),
+                                                                          int(sizes[j, 1]))
+            tasks.append((img, t["transform"], t["n"], t["r"], hk.numpy().copy(),
+                          hr.numpy().copy(), int(sse[i])))
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as wp:
+            good = wp.map(_c4_check, tasks, chunksize=1)
+        check = "ok" if all(good) else f"{len(good) - sum(good)} of {len(good)} mismatches"
+        log(f"oracle check of {len(tasks)} sampled requests ({100 * len(tasks) / n_req:.1f} %): "
+            f"{check}")
+
+    sweep = []
+    for rate in [float(v) for v in args.sweep.split(",") if v.strip()]:
+        m = int(rate * 1.0)
+        tr = synth.serving_requests(m, seed=4001, rate_hz=rate)
+        res, _, _ = replay(tr, rate)
+        sweep.append(res)
+        log(f"sweep {rate:.0f}/s: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms, "
+            f"served {res['served_gpixel_s']} of offered {res['offered_gpixel_s']} Gpx/s, "
+            f"mean batch {res['mean_batch']}")
+        if res["served_gpixel_s"] < 0.8 * res["offered_gpixel_s"]:
+            break
+
+    out = {
+        "metric": METRIC,
+        "value": main_res["served_gpixel_s"],
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(args.duration * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded Poisson trace, pool of AR(1) uint8 images)",
+        "config": {"workload": f"serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s "
+                               f"({n_req} requests), sides log-normal (median 1024) in "
+                               f"[64, 4096], T1/T2, N in {{8,16,32}}, r in 6..28, "
+                               f"{args.budget_gb:.0f} GB budget",
+                   "pool_images": pool_n},
+        "latency_ms": {"p50": main_res["p50_ms"], "p99": main_res["p99_ms"],
+                       "max": main_res["max_ms"]},
+        "serving": main_res,
+        "sweep": sweep,
+        "roofline": None,
         "parity_sample": check,
         "cpu_baseline": None,
     }

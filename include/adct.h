@@ -235,15 +235,18 @@ ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
  * queued as one batch whenever one of its max_inflight batch slots is free:
  * one launch per (transform, n, dtype, quantiser, r class) covering every
  * request of that class in the batch.  Requests that arrive while batches
- * run join the next batch, so the batch size follows the load.
+ * run join the next batch, so the batch size follows the load.  Each slot
+ * has its own stream, ordered after the caller's stream at every flush, so
+ * consecutive batches run side by side on the device and may complete out
+ * of order.
  *
  * Memory.  The server owns a device arena of budget_bytes for the outputs
  * (reconstruction with the request's pitch, retained coefficients, optional
  * scaled coefficients), allocated at the first flush.  A request is charged
  * its input plus its outputs; adct_server_submit returns ADCT_E_BUDGET when
  * the charge does not fit next to the requests in flight (retry after a
- * poll), or when it exceeds the whole budget.  Batches complete in
- * submission order, so the arena is a ring.
+ * poll), or when it exceeds the whole budget.  The arena is a ring: a
+ * block is reused once every older block has been released.
  *
  * Time.  done_ms and adct_server_clock_ms use one clock: milliseconds of the
  * host's steady clock since the server was created.  A batch's completion
@@ -301,8 +304,9 @@ ADCT_API int adct_server_submit(adct_server_t* server, const adct_request_t* req
  * launched (0 when nothing is queued or every slot is busy). */
 ADCT_API int adct_server_flush(adct_server_t* server, int* launched);
 
-/* Report completed batches, oldest first, as long as their requests fit in
- * out[0 .. max_out) (max_out must be at least max_batch).  wait != 0 blocks
+/* Report completed batches (in launch order among those complete) as long as
+ * their requests fit in out[0 .. max_out) (max_out must be at least
+ * max_batch).  wait != 0 blocks
  * until every launched batch has completed.  Arena space of the batches
  * reported by the previous poll is released first. */
 ADCT_API int adct_server_poll(adct_server_t* server, int wait, adct_completion_t* out,
@@ -319,11 +323,12 @@ ADCT_API double adct_server_clock_ms(const adct_server_t* server);
  * arrives arrival_ms[i] milliseconds after the start (non-decreasing), is
  * admitted in arrival order (waiting while the budget is full), batched and
  * launched; the call returns when every request has completed.
- * latency_ms[i] = completion - arrival, batch_of[i] = its batch (either may be
- * NULL).  A request that fails validation gets latency NaN and batch -1. */
+ * latency_ms[i] = completion - arrival, batch_of[i] = its batch, sse[i] = its
+ * error energy (any of the three may be NULL).  A request that fails
+ * validation gets latency NaN and batch -1.  The server must be idle. */
 ADCT_API int adct_server_run_trace(adct_server_t* server, const adct_request_t* requests,
                                    const double* arrival_ms, int64_t n, double* latency_ms,
-                                   int64_t* batch_of);
+                                   int64_t* batch_of, uint64_t* sse);
 
 #ifdef __cplusplus
 }

@@ -343,12 +343,13 @@ class Server:
 
     def run_trace(self, requests, arrival_ms):
         """Replay an arrival trace in real time (native loop); returns
-        (latency_ms, batch_of) arrays."""
+        (latency_ms, batch_of, sse) arrays."""
         reqs = np.ascontiguousarray(requests, dtype=REQUEST)
         arr = np.ascontiguousarray(arrival_ms, dtype=np.float64)
         lat = np.zeros(len(reqs), dtype=np.float64)
         bat = np.zeros(len(reqs), dtype=np.int64)
+        sse = np.zeros(len(reqs), dtype=np.uint64)
         _lib.check(_lib.load().adct_server_run_trace(self._h, reqs.ctypes.data, arr.ctypes.data,
                                                      len(reqs), lat.ctypes.data,
-                                                     bat.ctypes.data))
-        return lat, bat
+                                                     bat.ctypes.data, sse.ctypes.data))
+        return lat, bat, sse

@@ -42,7 +42,7 @@ _SIGNATURES = {
     "adct_server_poll": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "adct_server_stats": ([_vp, _vp], _i32),
     "adct_server_clock_ms": ([_vp], C.c_double),
-    "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp], _i32),
+    "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp], _i32),
 }
 
 ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE = 0, 1, 2

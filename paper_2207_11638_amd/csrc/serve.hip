@@ -7,13 +7,17 @@
 // the host only.
 //
 // Batches.  adct_server_flush takes the queued requests (oldest first) into a
-// free batch slot and issues, on the server's stream: the request tables
-// (pinned host -> device), a clear of the per-request error energies, one
-// launch per class (transform, n, dtype, quantiser, r bound) covering all of
-// that class's requests, the copy of the error energies back to pinned host
-// memory, the optional host copies of outputs, and the slot's completion
-// event.  Requests that arrive while batches run wait in the queue and form
-// the next batch: the batch size follows the load.
+// free batch slot.  Each slot has its own stream, ordered after the caller's
+// stream, on which it issues: the request tables (pinned host -> device), a
+// clear of the per-request error energies, one launch per class (transform,
+// n, dtype, quantiser, r bound) covering all of that class's requests, the
+// copy of the error energies back to pinned host memory, the optional host
+// copies of outputs, and the slot's completion event.  Requests that arrive
+// while batches run wait in the queue and form the next batch, which runs
+// on another slot's stream beside the batches still on the device: the
+// batch size follows the load and consecutive batches overlap.  Batches may
+// therefore complete out of order; an arena block is reused once every
+// older block has been released.
 //
 // Class launches.  Workgroup i of a class launch processes one tile group
 // (64 8x8 tiles, or 256/n tiles of size n) of one request.  The request is
@@ -176,7 +180,8 @@ int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 struct Member {
   adct_request_t req;
   int64_t charge = 0;     // budget bytes (input + outputs)
-  int64_t off = 0;        // arena block
+  int64_t seq = 0;        // arena block: allocation number, offset, length
+  int64_t off = 0;
   int64_t len = 0;
   int64_t recon_off = 0, kept_off = 0, scaled_off = -1;
   int table = 0;          // index in the batch's request table
@@ -189,9 +194,16 @@ struct Slot {
   SReq* h_reqs = nullptr;
   int* h_begins = nullptr;
   unsigned long long* h_sse = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;    // recorded on the caller's stream at flush
   hipEvent_t done = nullptr;
   std::vector<Member> members;   // submission order
   int64_t id = -1;
+};
+
+struct Block {
+  int64_t off, len;
+  bool freed;
 };
 
 int hip_fail(hipError_t e, const char* what) {
@@ -211,13 +223,14 @@ struct adct_server {
   int max_batch = 1;
   hipStream_t stream = nullptr;
   std::chrono::steady_clock::time_point t0;
-  // arena ring: live blocks (offset, length) in allocation order
+  // arena ring: blocks in allocation order; block seq is live[seq - seq_front]
   char* arena = nullptr;
-  std::deque<std::pair<int64_t, int64_t>> live;
+  std::deque<Block> live;
+  int64_t seq_front = 0;
   int64_t charged = 0;
   std::deque<Member> queue;
   std::vector<Slot> slots;
-  std::deque<int> inflight;       // slot indices, launch order
+  std::vector<int> inflight;      // slot indices, launch order
   std::vector<int> free_slots;
   std::vector<Member> to_release; // reported by the last poll
   int64_t next_batch = 0;
@@ -232,21 +245,32 @@ struct adct_server {
         .count();
   }
 
-  bool ring_alloc(int64_t len, int64_t* off) {
+  // Reserve len bytes after the newest block, wrapping to offset 0 when the
+  // end of the arena is reached; space is free up to the oldest live block.
+  bool ring_alloc(int64_t len, int64_t* off, int64_t* seq) {
     if (len > budget) return false;
     if (live.empty()) {
       *off = 0;
     } else {
-      const int64_t oldest = live.front().first;
-      const int64_t end = live.back().first + live.back().second;
-      const bool wrapped = live.back().first < oldest;
+      const int64_t oldest = live.front().off;
+      const int64_t end = live.back().off + live.back().len;
+      const bool wrapped = live.back().off < oldest;
       if (!wrapped && end + len <= budget) *off = end;
       else if (!wrapped && len <= oldest) *off = 0;
       else if (wrapped && end + len <= oldest) *off = end;
       else return false;
     }
-    live.emplace_back(*off, len);
+    *seq = seq_front + static_cast<int64_t>(live.size());
+    live.push_back(Block{*off, len, false});
     return true;
+  }
+
+  void ring_release(int64_t seq) {
+    live[seq - seq_front].freed = true;
+    while (!live.empty() && live.front().freed) {
+      live.pop_front();
+      ++seq_front;
+    }
   }
 };
 
@@ -314,12 +338,22 @@ int ensure_device(adct_server* s) {
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_begins), nb * sizeof(int), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_sse), nb * 8, 0);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "batch slot allocation");
     s->free_slots.push_back(s->max_inflight - 1 - i);
   }
+  // Clock alignment: the origin event's host time is taken as the moment its
+  // completion is observed, by spinning on the query.  That is no earlier
+  // than the event itself, so completion times derived from it (and the
+  // latencies) err on the late side, by the observation delay.
   e = hipEventCreate(&s->origin);
   if (e == hipSuccess) e = hipEventRecord(s->origin, s->stream);
-  if (e == hipSuccess) e = hipEventSynchronize(s->origin);
+  while (e == hipSuccess) {
+    e = hipEventQuery(s->origin);
+    if (e == hipErrorNotReady) e = hipSuccess;
+    else break;
+  }
   if (e != hipSuccess) return hip_fail(e, "clock origin");
   s->origin_ms = s->clock_ms();
   s->device_ready = true;
@@ -374,7 +408,7 @@ int do_submit(adct_server* s, const adct_request_t* req) {
     ++s->n_refused;
     return set_error(ADCT_E_BUDGET, "server: request exceeds the whole budget");
   }
-  if (s->charged + m.charge > s->budget || !s->ring_alloc(m.len, &m.off)) {
+  if (s->charged + m.charge > s->budget || !s->ring_alloc(m.len, &m.off, &m.seq)) {
     ++s->n_refused;
     return set_error(ADCT_E_BUDGET, "server: budget full, retry after a poll");
   }
@@ -434,18 +468,21 @@ int do_flush(adct_server* s, int* launched) {
     ++L.count;
     mb.table = t;
   }
-  hipError_t e = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, m * sizeof(SReq), hipMemcpyHostToDevice,
-                                s->stream);
+  // the slot's work follows whatever the caller's stream has queued (the inputs)
+  const hipStream_t st = sl.stream;
+  hipError_t e = hipEventRecord(sl.ready, s->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, sl.ready, 0);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.d_begins, sl.h_begins, m * sizeof(int), hipMemcpyHostToDevice,
-                       s->stream);
+    e = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, m * sizeof(SReq), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.d_begins, sl.h_begins, m * sizeof(int), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "request table upload");
-  clear_u64<<<(m + 255) / 256, 256, 0, s->stream>>>(sl.d_sse, m);
+  clear_u64<<<(m + 255) / 256, 256, 0, st>>>(sl.d_sse, m);
   for (const Launch& L : launches)
-    launch_class(L.key, L.items, s->stream, sl.d_reqs + L.first, sl.d_begins + L.first, L.count);
+    launch_class(L.key, L.items, st, sl.d_reqs + L.first, sl.d_begins + L.first, L.count);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "class launch");
-  e = hipMemcpyAsync(sl.h_sse, sl.d_sse, m * 8, hipMemcpyDeviceToHost, s->stream);
+  e = hipMemcpyAsync(sl.h_sse, sl.d_sse, m * 8, hipMemcpyDeviceToHost, st);
   for (int i = 0; i < m && e == hipSuccess; ++i) {
     const Member& mb = sl.members[i];
     const adct_request_t& q = mb.req;
@@ -453,17 +490,17 @@ int do_flush(adct_server* s, int* launched) {
     if (q.h_kept != nullptr)
       e = hipMemcpyAsync(q.h_kept, s->arena + mb.off + mb.kept_off,
                          static_cast<int64_t>(q.height / q.n) * (q.width / q.n) * q.r * 4,
-                         hipMemcpyDeviceToHost, s->stream);
+                         hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && q.h_scaled != nullptr)
       e = hipMemcpyAsync(q.h_scaled, s->arena + mb.off + mb.scaled_off,
                          static_cast<int64_t>(q.height / q.n) * (q.width / q.n) * q.r * 4,
-                         hipMemcpyDeviceToHost, s->stream);
+                         hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && q.h_recon != nullptr)
       e = hipMemcpyAsync(q.h_recon, s->arena + mb.off + mb.recon_off,
                          static_cast<int64_t>(q.height) * q.pitch * esize, hipMemcpyDeviceToHost,
-                         s->stream);
+                         st);
   }
-  if (e == hipSuccess) e = hipEventRecord(sl.done, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, st);
   if (e != hipSuccess) return hip_fail(e, "batch completion");
   s->queue.erase(s->queue.begin(), s->queue.begin() + m);
   s->free_slots.pop_back();
@@ -474,18 +511,25 @@ int do_flush(adct_server* s, int* launched) {
   return set_error(ADCT_OK, "");
 }
 
+// Report the completed batches (in launch order among those complete) while
+// their requests fit in out.
 int do_poll(adct_server* s, int wait, adct_completion_t* out, int max_out, int* n_out) {
   if (n_out) *n_out = 0;
   for (const Member& mb : s->to_release) {
-    s->live.pop_front();
+    s->ring_release(mb.seq);
     s->charged -= mb.charge;
   }
   s->to_release.clear();
   int n = 0;
-  while (!s->inflight.empty()) {
-    Slot& sl = s->slots[s->inflight.front()];
+  size_t i = 0;
+  while (i < s->inflight.size()) {
+    const int slot_id = s->inflight[i];
+    Slot& sl = s->slots[slot_id];
     hipError_t e = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
-    if (e == hipErrorNotReady) break;
+    if (e == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
     if (e != hipSuccess) return hip_fail(e, "batch completion");
     if (n + static_cast<int>(sl.members.size()) > max_out) break;
     float ms = 0.f;
@@ -507,8 +551,8 @@ int do_poll(adct_server* s, int wait, adct_completion_t* out, int max_out, int* 
     }
     s->n_completed += static_cast<int64_t>(sl.members.size());
     sl.members.clear();
-    s->free_slots.push_back(s->inflight.front());
-    s->inflight.pop_front();
+    s->free_slots.push_back(slot_id);
+    s->inflight.erase(s->inflight.begin() + i);
   }
   if (n_out) *n_out = n;
   return set_error(ADCT_OK, "");
@@ -550,6 +594,8 @@ ADCT_API int adct_server_destroy(adct_server_t* s) {
     if (sl.h_begins) (void)hipHostFree(sl.h_begins);
     if (sl.h_sse) (void)hipHostFree(sl.h_sse);
     if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.ready) (void)hipEventDestroy(sl.ready);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   if (s->origin) (void)hipEventDestroy(s->origin);
   if (s->arena) (void)hipFree(s->arena);
@@ -596,7 +642,7 @@ ADCT_API double adct_server_clock_ms(const adct_server_t* s) {
 
 ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* requests,
                                    const double* arrival_ms, int64_t n, double* latency_ms,
-                                   int64_t* batch_of) {
+                                   int64_t* batch_of, uint64_t* sse) {
   if (s == nullptr || n < 0 || (n > 0 && (requests == nullptr || arrival_ms == nullptr)))
     return set_error(ADCT_E_ARG, "server: bad trace arguments");
   for (int64_t i = 1; i < n; ++i)
@@ -609,6 +655,7 @@ ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* reque
   for (int64_t i = 0; i < n; ++i) {
     if (latency_ms) latency_ms[i] = NAN;
     if (batch_of) batch_of[i] = -1;
+    if (sse) sse[i] = 0;
   }
   std::vector<adct_completion_t> done(s->max_batch);
   std::deque<int64_t> waiting;
@@ -622,6 +669,7 @@ ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* reque
       const int64_t i = done[k].tag;
       if (latency_ms) latency_ms[i] = done[k].done_ms - (start + arrival_ms[i]);
       if (batch_of) batch_of[i] = done[k].batch;
+      if (sse) sse[i] = done[k].sse;
     }
     finished += got;
     progress |= got > 0;

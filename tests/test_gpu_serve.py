@@ -177,7 +177,7 @@ def test_trace_replay():
     arrival_ms = synth.poisson_arrivals(len(jobs), rate_hz=20000.0, seed=22) * 1e3
     reqs = np.stack([j.rec for j in jobs])
     srv = adct.Server(1 << 22, max_inflight=2, max_batch=64, stream=stream())
-    lat, batch = srv.run_trace(reqs, arrival_ms)
+    lat, batch, sse = srv.run_trace(reqs, arrival_ms)
     st = srv.stats()
     srv.close()
     assert np.all(np.isfinite(lat)) and np.all(lat > 0)
@@ -188,3 +188,4 @@ def test_trace_replay():
         got = j.outputs()
         assert np.array_equal(got["kept"], want["kept"]), j.tag
         assert np.array_equal(got["recon"], want["recon"]), j.tag
+        assert int(sse[j.tag]) == want["sse"], j.tag

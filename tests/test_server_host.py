@@ -125,7 +125,7 @@ def test_trace_arguments():
     reqs = np.stack([req(), req()])
     with pytest.raises(adct.AdctError):
         srv.run_trace(reqs, np.array([1.0, 0.5]))      # decreasing arrivals
-    lat, bat = srv.run_trace(reqs[:0], np.zeros(0))    # empty trace: no device work
+    lat, bat, sse = srv.run_trace(reqs[:0], np.zeros(0))    # empty trace: no device work
     assert len(lat) == 0 and len(bat) == 0
     srv.close()
 
