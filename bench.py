@@ -157,6 +157,9 @@ def main():
                     help="c1: the 1024 x 2048^2 sweep (default); c3: the ragged batch; "
                          "c4: the serving loop; "
                          "plain: one fused configuration (--n, --transform, --r, --qstep)")
+    ap.add_argument("--engine", choices=("butterfly", "mfma"), default="butterfly",
+                    help="c1/plain: N=8 uint8 zonal passes on the butterflies or on the int8 "
+                         "matrix cores")
     ap.add_argument("--rate", type=float, default=2000.0, help="c4: arrivals per second")
     ap.add_argument("--duration", type=float, default=30.0, help="c4: trace length (s)")
     ap.add_argument("--pool", type=int, default=64, help="c4: device-resident images")
@@ -244,7 +247,8 @@ def run_c1(args):
             kv, sv = views(r)
             if events is not None:
                 events[i][0].record()
-            adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse)
+            adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse,
+                          engine=args.engine)
             if events is not None:
                 events[i][1].record()
 
@@ -289,7 +293,7 @@ def run_c1(args):
         k, r = 2, 10
         kv, sv = views(r)
         sse.zero_()
-        adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse)
+        adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse, engine=args.engine)
         torch.cuda.synchronize()
         bad = 0
         for i in sorted({0, b // 2, b - 1}):
@@ -310,7 +314,10 @@ def run_c1(args):
         log("timing the CPU oracle on a sample")
         cpu = cpu_baseline(h, w)
 
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.engine == "butterfly" else None
+    kernel = ("compress8 (fused 8x8 kernel; 14 instantiations, one per (T, r))"
+              if args.engine == "butterfly" else
+              "compress8_mfma (fused 8x8 kernel on the int8 matrix cores)")
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -327,12 +334,13 @@ def run_c1(args):
         "config": {"workload": f"plain method at scale: {b} x {h}x{w} uint8 AR(1) images, N=8, "
                                "T1+T2 x r in {1,6,10,16,28,45,64}, fused fwd+retain+scale+inv+SSE",
                    "images": b, "height": h, "width": w, "n": N, "r_sweep": list(SWEEP_R),
-                   "outputs": "kept int32 + scaled float32 + recon uint8 + sse"},
+                   "outputs": "kept int32 + scaled float32 + recon uint8 + sse",
+                   "engine": args.engine},
         "blocks_per_s": round(tiles * len(combos) * args.steps / (total_ms / 1e3), 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "compress8 (fused 8x8 kernel; 14 instantiations, one per (T, r))"},
+                     "kernel": kernel},
         "kernels": kernels,
         "parity_sample": check,
         "cpu_baseline": cpu,
@@ -365,7 +373,7 @@ def run_plain(args):
 
     def step():
         adct.compress(x, args.transform, n, r, args.qstep, kept=kept, scaled=scaled, recon=recon,
-                      sse=sse)
+                      sse=sse, engine=args.engine)
 
     for _ in range(args.warmup):
         step()

@@ -146,6 +146,18 @@ ADCT_API int adct_decompress(int transform, int n, int r, int qstep, const int32
                              void* d_dst, int dtype, int batch, int height, int width,
                              int64_t pitch, int64_t image_stride, adct_stream_t stream);
 
+/* The fused compress of adct_compress for n = 8, ADCT_U8 and zonal
+ * retention (qstep 0), computed on the int8 matrix cores instead of the
+ * butterflies: vec(B) = (T (x) T) vec(A - 128) and the exact inverse
+ * vec(X) = (U (x) U) vec(B~) with U = 8 T^-1 (section 3, eqs. 4-7), both
+ * Kronecker products having entries in {0, +-1, +-2, +-4}.  Arguments,
+ * layouts and outputs are those of adct_compress (outputs bit-identical);
+ * image rows must be 8-byte aligned. */
+ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int batch, int height,
+                                int width, int64_t pitch, int64_t image_stride, int32_t* d_kept,
+                                float* d_scaled, void* d_recon, uint64_t* d_sse,
+                                adct_stream_t stream);
+
 /* ----------------------------------------------------------------------
  * Ragged batches: many images of different sizes, each partitioned into
  * square transform units (TUs) of 8, 16 or 32 pixels (an HEVC-style quadtree;

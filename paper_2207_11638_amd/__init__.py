@@ -125,11 +125,14 @@ def inv2d(coef, transform: int, n: int, r: int, qstep: int = 0, dtype=None, out=
 
 
 def compress(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True, scaled=True,
-             recon=True, sse=True):
+             recon=True, sse=True, engine: str = "butterfly"):
     """The fused pipeline.  Each of kept/scaled/recon/sse may be True (allocate),
     False (skip) or a preallocated tensor.  Returns a dict of the produced
     tensors: kept int32 [B, H/n, W/n, r], scaled float32 [B, H/n, W/n, r],
-    recon like x, sse uint64 [B] (accumulated into when passed in)."""
+    recon like x, sse uint64 [B] (accumulated into when passed in).
+    engine="mfma" runs the int8 matrix-core form (n = 8, uint8, qstep = 0)."""
+    if engine not in ("butterfly", "mfma"):
+        raise ValueError(f"unknown engine {engine!r}")
     torch = _torch()
     _require_device(x)
     b, h, w, pitch, istride = _image_geometry(x)
@@ -153,9 +156,16 @@ def compress(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True, sc
         rb, rh, rw, rp, rs = _image_geometry(recon_t)
         if (rb, rh, rw, rp, rs) != (b, h, w, pitch, istride):
             raise ValueError("recon must have the geometry of x")
-    _lib.check(_lib.load().adct_compress(transform, n, r, qstep, _ptr(x), _dtype_code(x), b, h,
-                                         w, pitch, istride, _ptr(kept_t), _ptr(scaled_t),
-                                         _ptr(recon_t), _ptr(sse_t), _stream_handle(dev)))
+    if engine == "mfma":
+        if n != 8 or qstep != 0 or x.dtype != torch.uint8:
+            raise ValueError("the mfma engine takes n = 8, uint8 images and qstep = 0")
+        _lib.check(_lib.load().adct_compress_mfma(transform, r, _ptr(x), b, h, w, pitch, istride,
+                                                  _ptr(kept_t), _ptr(scaled_t), _ptr(recon_t),
+                                                  _ptr(sse_t), _stream_handle(dev)))
+    else:
+        _lib.check(_lib.load().adct_compress(transform, n, r, qstep, _ptr(x), _dtype_code(x), b,
+                                             h, w, pitch, istride, _ptr(kept_t), _ptr(scaled_t),
+                                             _ptr(recon_t), _ptr(sse_t), _stream_handle(dev)))
     return {"kept": kept_t, "scaled": scaled_t, "recon": recon_t, "sse": sse_t}
 
 

@@ -29,6 +29,8 @@ _SIGNATURES = {
                          _vp], _i32),
     "adct_compress": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp,
                        _vp, _vp, _vp], _i32),
+    "adct_compress_mfma": ([_i32, _i32, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
+                            _vp], _i32),
     "adct_batch_create": ([_vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp], _i32),
     "adct_batch_destroy": ([_vp], _i32),
     "adct_batch_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),

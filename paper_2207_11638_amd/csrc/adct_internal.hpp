@@ -82,5 +82,9 @@ enum class Mode : int { Compress = 0, Forward = 1, Inverse = 2, Decompress = 3 }
 // Kernel launchers (return hipError_t as int).
 int launch_n8(Mode mode, int kind, int dtype, const PassParams& p, hipStream_t stream);
 int launch_jam(Mode mode, int kind, int n, int dtype, const PassParams& p, hipStream_t stream);
+// Fused 8x8 compress (uint8, zonal) on the int8 matrix cores; t = T[v][i] and
+// u = (8 T^-1)[i][v], row-major.
+int launch_n8_mfma(int kind, const PassParams& p, const int8_t* t, const int8_t* u,
+                   hipStream_t stream);
 
 }  // namespace adct

@@ -332,4 +332,46 @@ ADCT_API int adct_compress(int transform, int n, int r, int qstep, const void* d
   return launch(Mode::Compress, transform, n, dtype, p, stream);
 }
 
+ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int batch, int height,
+                                int width, int64_t pitch, int64_t image_stride, int32_t* d_kept,
+                                float* d_scaled, void* d_recon, uint64_t* d_sse,
+                                adct_stream_t stream) {
+  const int n = 8;
+  if (int s = check_common(transform, n)) return s;
+  if (int s = check_r_q(n, r, 0)) return s;
+  PassParams p{};
+  if (int s = check_images("compress_mfma", n, ADCT_U8, d_src, batch, height, width, pitch,
+                           image_stride, p.g))
+    return s;
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  if (d_src == nullptr) return fail(ADCT_E_ARG, "compress_mfma: null source");
+  if ((reinterpret_cast<uintptr_t>(d_recon) % 8) || (reinterpret_cast<uintptr_t>(d_kept) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_scaled) % 4) || (reinterpret_cast<uintptr_t>(d_sse) % 8))
+    return fail(ADCT_E_ALIGN, "compress_mfma: misaligned output buffer");
+  TableSet ts;
+  if (int s = build_tables(transform, n, 0, ts)) return s;
+  p.t = ts.t;
+  p.src = d_src;
+  p.dst = d_recon;
+  p.cout = d_kept;
+  p.scaled = d_scaled;
+  p.sse = reinterpret_cast<unsigned long long*>(d_sse);
+  p.r = r;
+  std::vector<int> fwd, inv;
+  operator_matrix(transform, n, false, fwd);
+  operator_matrix(transform, n, true, inv);
+  int8_t t8m[64], u8m[64];
+  for (int i = 0; i < 64; ++i) {
+    // the inverse butterfly applies 2 U; U = 8 T^-1 has entries in {0, +-1, +-2}
+    if (fwd[i] < -2 || fwd[i] > 2 || inv[i] % 2 || inv[i] < -4 || inv[i] > 4)
+      return fail(ADCT_E_ARG, "internal: matrix entry outside the int8 operand range");
+    t8m[i] = static_cast<int8_t>(fwd[i]);
+    u8m[i] = static_cast<int8_t>(inv[i] / 2);
+  }
+  const int e = launch_n8_mfma(transform, p, t8m, u8m, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
 }  // extern "C"

@@ -1,0 +1,252 @@
+// 8 x 8 fused compress on the matrix cores: an alternative to the butterfly
+// kernel for 8-bit images with zonal retention.
+//
+// With vec(A) the 64 pixels of a tile in row-major order, the forward 2D
+// transform B = T A T^T is vec(B) = (T (x) T) vec(A), and the exact inverse
+// X = U B~ U^T (U = 8 T^-1, integral) is vec(X) = (U (x) U) vec(B~).  The
+// entries of T and U lie in {0, +-1, +-2}, so both Kronecker products have
+// entries in {0, +-1, +-2, +-4}: int8 operands.  A - 128 is int8 (a byte XOR
+// with 0x80).  |B| <= 8192 does not fit int8, so the inverse takes
+// B~ = 128 hi + lo (lo in [0, 127], hi in [-64, 64]) as two int8 operands and
+// combines the two int32 products exactly.  Everything stays exact in int32.
+//
+// v_mfma_i32_16x16x64_i8: D[16][16] = A[16][64] B[64][16].  Lane l holds row
+// (or column) l % 16 and K = 16 (l / 16) .. + 15 of the A (B) operand, and
+// D[4 (l / 16) + t][l % 16] in accumulator t.  One wave handles 16 tiles per
+// step (column j = tile j):
+//   forward  B operand: lane group q = l / 16 loads rows 2q, 2q+1 of tile
+//            l % 16 (two 8-byte loads), so K = pixel index.  Four MFMAs (one
+//            per block of 16 coefficients) leave coefficient
+//            c = 16 blk + 4 q + t of tile l % 16 in lane l, accumulator t of
+//            block blk.
+//   inverse  B operand: the lane's own 16 coefficients, K slot
+//            16 q + 4 blk + t; the columns of U (x) U are permuted to match,
+//            so no value changes lanes.  The rows are permuted so that block
+//            blk2 leaves pixel 16 q + 4 blk2 + t (rows 2q, 2q+1) in lane l:
+//            the reconstruction is stored with the same two 8-byte accesses
+//            that loaded the tile, and the error energy needs no exchange.
+// The zig-zag outputs (kept int32, scaled float32) of a step's 16 tiles go
+// through LDS so that consecutive lanes store consecutive words.  A wave
+// walks up to 256 tiles of its tile row, so that building the operands (128
+// small products per lane) is paid once per 16 steps.
+#include "tile8.hpp"
+
+namespace adct {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kWaveSize = 64;
+
+struct MfmaParams {
+  PassParams p;
+  int8_t t[64];   // T[v][i], row-major
+  int8_t u[64];   // U[i][v] = (8 T^-1)[i][v], row-major
+};
+
+constexpr int kStage = 65;   // LDS words per staged tile (odd: distinct banks);
+                             // word 64 takes the coefficients outside the prefix
+constexpr int kTilesPerWave = 256;
+
+__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
+  return (static_cast<uint32_t>(a) & 0xffu) | ((static_cast<uint32_t>(b) & 0xffu) << 8) |
+         ((static_cast<uint32_t>(c) & 0xffu) << 16) | (static_cast<uint32_t>(d) << 24);
+}
+
+// Lane -> (tile, word) walk over a staged block of ntiles x r words: lane e
+// copies word k of tile t for e = lane, lane + 64, ...; (t0, k0) and the
+// step (dt, dk) depend on r only.
+struct StageWalk {
+  int t0, k0, dt, dk;
+};
+
+__device__ __forceinline__ StageWalk stage_walk(int r, int lane) {
+  StageWalk w;
+  w.t0 = lane / r;
+  w.k0 = lane - w.t0 * r;
+  w.dt = kWaveSize / r;
+  w.dk = kWaveSize - w.dt * r;
+  return w;
+}
+
+// Copy the staged words st[t * kStage + k] (t < ntiles, k < r) to g[t * r + k].
+__device__ __forceinline__ void copy_stage(uint32_t* g, const int* st, int ntiles, int r,
+                                           const StageWalk& w, int lane) {
+  int t = w.t0, k = w.k0;
+  for (int e = lane; e < ntiles * r; e += kWaveSize) {
+    g[e] = static_cast<uint32_t>(st[t * kStage + k]);
+    k += w.dk;
+    t += w.dt;
+    if (k >= r) {
+      k -= r;
+      ++t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void compress8_mfma(MfmaParams mp) {
+  const PassParams& p = mp.p;
+  __shared__ int8_t tab[128];
+  __shared__ int stage[16 * kStage];
+  const int lane = threadIdx.x;
+  const int q = lane >> 4;
+  const int col = lane & 15;
+  tab[lane] = mp.t[lane];
+  tab[64 + lane] = mp.u[lane];
+  __syncthreads();
+
+  // operands of the two Kronecker products, one v4i per block of 16 rows
+  v4i fa[4], ia[4];
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int v = 2 * blk + (col >> 3), u = col & 7;              // forward row: coefficient
+    const int pi = 2 * (col >> 2) + (blk >> 1);                   // inverse row: pixel
+    const int pj = 4 * (blk & 1) + (col & 3);
+    uint32_t fw[4], iw[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      int f[4], g[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int b = 4 * w + e;
+        const int fi = 2 * q + (b >> 3), fj = b & 7;              // forward K: pixel
+        f[e] = tab[v * 8 + fi] * tab[u * 8 + fj];
+        const int s = 16 * (b >> 2) + 4 * q + (b & 3);           // inverse K: coefficient
+        g[e] = tab[64 + pi * 8 + (s >> 3)] * tab[64 + pj * 8 + (s & 7)];
+      }
+      fw[w] = pack4(f[0], f[1], f[2], f[3]);
+      iw[w] = pack4(g[0], g[1], g[2], g[3]);
+    }
+    fa[blk] = v4i{static_cast<int>(fw[0]), static_cast<int>(fw[1]), static_cast<int>(fw[2]),
+                  static_cast<int>(fw[3])};
+    ia[blk] = v4i{static_cast<int>(iw[0]), static_cast<int>(iw[1]), static_cast<int>(iw[2]),
+                  static_cast<int>(iw[3])};
+  }
+
+  // zig-zag position and scale of each coefficient this lane holds
+  const int r = p.r;
+  int zpos[16];
+  float s2[16];
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int v = 2 * blk + (q >> 1), u = 4 * (q & 1) + t;
+      zpos[4 * blk + t] = zz_pos(8, v, u);
+      s2[4 * blk + t] = p.scaled != nullptr ? p.t.s2[p.t.cls[v] * 4 + p.t.cls[u]] : 0.f;
+    }
+
+  // staged position of each coefficient: its zig-zag slot, or the pad word
+  int slot[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) slot[k] = col * kStage + (zpos[k] < r ? zpos[k] : 64);
+  const StageWalk walk = stage_walk(r, lane);
+
+  const int tx0 = blockIdx.x * kTilesPerWave;
+  const int ty = blockIdx.y;
+  const int img = blockIdx.z;
+  const int nact = min(kTilesPerWave, p.g.tiles_x - tx0);
+  const int64_t row0 = static_cast<int64_t>(img) * p.g.image_stride +
+                       static_cast<int64_t>(ty) * 8 * p.g.pitch;
+  const int64_t tile_base = (static_cast<int64_t>(img) * p.g.tiles_y + ty) * p.g.tiles_x + tx0;
+  const uint8_t* src = static_cast<const uint8_t*>(p.src);
+  uint8_t* dst = static_cast<uint8_t*>(p.dst);
+  const v4i zero = {0, 0, 0, 0};
+  unsigned long long err = 0;
+
+  for (int gi = 0; gi * 16 < nact; ++gi) {
+    const int ng = min(16, nact - 16 * gi);
+    const bool active = col < ng;
+    const int64_t off0 = row0 + (2 * q) * p.g.pitch + static_cast<int64_t>(tx0 + 16 * gi + col) * 8;
+    const int64_t off1 = off0 + p.g.pitch;
+    uint2 r0 = make_uint2(0x80808080u, 0x80808080u), r1 = r0;
+    if (active) {
+      r0 = *reinterpret_cast<const uint2*>(src + off0);
+      r1 = *reinterpret_cast<const uint2*>(src + off1);
+    }
+    const v4i px = {static_cast<int>(r0.x ^ 0x80808080u), static_cast<int>(r0.y ^ 0x80808080u),
+                    static_cast<int>(r1.x ^ 0x80808080u), static_cast<int>(r1.y ^ 0x80808080u)};
+    int c[16];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const v4i d = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[blk], px, zero, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) c[4 * blk + t] = d[t];
+    }
+    const int64_t out0 = (tile_base + 16 * gi) * r;
+    if (p.scaled != nullptr) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        stage[slot[k]] = __builtin_bit_cast(int, static_cast<float>(c[k]) * s2[k]);
+      __syncthreads();
+      copy_stage(reinterpret_cast<uint32_t*>(p.scaled + out0), stage, ng, r, walk, lane);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = zpos[k] < r ? c[k] : 0;
+    if (p.cout != nullptr) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) stage[slot[k]] = c[k];
+      __syncthreads();
+      copy_stage(reinterpret_cast<uint32_t*>(p.cout + out0), stage, ng, r, walk, lane);
+      __syncthreads();
+    }
+    if (dst == nullptr && p.sse == nullptr) continue;
+
+    // inverse: B~ = 128 hi + lo, K slot 4 blk + t of the lane's group
+    v4i hi, lo;
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const int* cb = c + 4 * blk;
+      hi[blk] = static_cast<int>(pack4(cb[0] >> 7, cb[1] >> 7, cb[2] >> 7, cb[3] >> 7));
+      lo[blk] = static_cast<int>(pack4(cb[0] & 127, cb[1] & 127, cb[2] & 127, cb[3] & 127));
+    }
+    int y[16];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const v4i xh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ia[blk], hi, zero, 0, 0, 0);
+      const v4i x = __builtin_amdgcn_mfma_i32_16x16x64_i8(ia[blk], lo, xh << 7, 0, 0, 0);
+      // X = 64 * reconstruction: round(X / 64) + 128, clipped
+#pragma unroll
+      for (int t = 0; t < 4; ++t) y[4 * blk + t] = round_shift_u8<6>(x[t]);
+    }
+    // rows 2q (blocks 0, 1) and 2q + 1 (blocks 2, 3)
+    const uint2 o0 = make_uint2(pack4(y[0], y[1], y[2], y[3]), pack4(y[4], y[5], y[6], y[7]));
+    const uint2 o1 = make_uint2(pack4(y[8], y[9], y[10], y[11]), pack4(y[12], y[13], y[14], y[15]));
+    if (dst != nullptr && active) {
+      st_stream(reinterpret_cast<uint2*>(dst + off0), o0);
+      st_stream(reinterpret_cast<uint2*>(dst + off1), o1);
+    }
+    if (p.sse != nullptr && active) {
+      uint32_t sxx = 0, syy = 0, sxy = 0;
+      const uint32_t xs[4] = {r0.x, r0.y, r1.x, r1.y};
+      const uint32_t ys[4] = {o0.x, o0.y, o1.x, o1.y};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sxx = __builtin_amdgcn_udot4(xs[k], xs[k], sxx, false);
+        syy = __builtin_amdgcn_udot4(ys[k], ys[k], syy, false);
+        sxy = __builtin_amdgcn_udot4(xs[k], ys[k], sxy, false);
+      }
+      err += sxx + syy - 2u * sxy;
+    }
+  }
+  if (p.sse != nullptr) block_add_sse<kWaveSize>(p.sse + img, err, nullptr);
+}
+
+}  // namespace
+
+int launch_n8_mfma(int kind, const PassParams& p, const int8_t* t, const int8_t* u,
+                   hipStream_t stream) {
+  (void)kind;   // the transform enters through t and u only
+  MfmaParams mp;
+  mp.p = p;
+  for (int i = 0; i < 64; ++i) {
+    mp.t[i] = t[i];
+    mp.u[i] = u[i];
+  }
+  const dim3 grid((p.g.tiles_x + kTilesPerWave - 1) / kTilesPerWave, p.g.tiles_y, p.g.batch);
+  compress8_mfma<<<grid, kWaveSize, 0, stream>>>(mp);
+  return hipGetLastError();
+}
+
+}  // namespace adct

@@ -233,3 +233,66 @@ def test_repeatable():
     b = adct.compress(x, M.ROUND, 16, 28)
     for k in ("kept", "scaled", "recon", "sse"):
         assert np.array_equal(host(a[k]), host(b[k]))
+
+
+# ------------------------------------------------- int8 matrix-core engine (N=8)
+def compare_compress_mfma(imgs, kind, r, x=None):
+    if x is None:
+        x = to_dev(np.stack(imgs))
+    out = adct.compress(x, kind, 8, r, engine="mfma")
+    want, sse = oracle_batch(imgs, kind, 8, r, 0)
+    assert np.array_equal(host(out["kept"]), want["kept"])
+    check_scaled(host(out["scaled"]), want["scaled"])
+    rec = host(out["recon"])
+    assert np.array_equal(rec.reshape(want["recon"].shape), want["recon"])
+    assert host(out["sse"]).astype(np.int64).tolist() == sse
+    return out
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("r", [1, 3, 6, 10, 11, 16, 28, 45, 50, 64])
+def test_mfma_matches_oracle(kind, r):
+    # 300 tiles per row: four full waves of 64 tiles and a partial one, whose
+    # last 16-tile step is partial as well
+    h, w = SHAPES[8]
+    compare_compress_mfma(u8_images(2, h, w, 300), kind, r)
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+def test_mfma_equals_butterflies_on_extremes(kind):
+    # saturated content drives the coefficients and the reconstruction to
+    # their limits (|b| up to 8192, clipping at 0 and 255)
+    rng = synth.rng_for(77)
+    imgs = [rng.choice(np.array([0, 255], dtype=np.uint8), size=(32, 8 * 70)) for _ in range(2)]
+    imgs.append(np.full((32, 8 * 70), 255, dtype=np.uint8))
+    imgs.append(np.zeros((32, 8 * 70), dtype=np.uint8))
+    x = to_dev(np.stack(imgs))
+    for r in (1, 10, 37, 64):
+        a = adct.compress(x, kind, 8, r, engine="mfma")
+        b = adct.compress(x, kind, 8, r)
+        for key in ("kept", "scaled", "recon", "sse"):
+            assert torch.equal(a[key], b[key]), (key, r)
+    compare_compress_mfma(imgs, kind, 45, x=x)
+
+
+def test_mfma_pitched_batch_and_partial_outputs():
+    imgs = u8_images(3, 24, 8 * 21, 400)
+    full = np.zeros((3, 24, 8 * 21 + 40), dtype=np.uint8)
+    full[:, :, : 8 * 21] = np.stack(imgs)
+    x = to_dev(full)[:, :, : 8 * 21]
+    compare_compress_mfma(imgs, 2, 21, x=x)
+    # only the reconstruction, only the coefficients
+    a = adct.compress(x, 1, 8, 10, engine="mfma", kept=False, scaled=False, sse=False)
+    b = adct.compress(x, 1, 8, 10, kept=False, scaled=False, sse=False)
+    assert torch.equal(a["recon"], b["recon"])
+    a = adct.compress(x, 1, 8, 10, engine="mfma", recon=False, sse=False)
+    b = adct.compress(x, 1, 8, 10, recon=False, sse=False)
+    assert torch.equal(a["kept"], b["kept"]) and torch.equal(a["scaled"], b["scaled"])
+
+
+def test_mfma_rejects_what_it_does_not_cover():
+    x = to_dev(np.stack(u8_images(1, 16, 16, 1)))
+    with pytest.raises(ValueError):
+        adct.compress(x, 1, 16, 10, engine="mfma")
+    with pytest.raises(ValueError):
+        adct.compress(x, 1, 8, 10, 16, engine="mfma")

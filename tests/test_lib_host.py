@@ -89,6 +89,22 @@ def test_empty_image_sets_are_a_no_op(lib):
     assert lib.adct_decompress(2, 8, 5, 0, None, None, 1, 1, 0, 8, 8, 0, None) == 0
 
 
+def test_mfma_entry_point_validates(lib):
+    p = C.c_void_p(4096)
+    #                              T  r   src  B  H   W   pitch stride kept scaled recon sse
+    assert lib.adct_compress_mfma(3, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
+    assert lib.adct_compress_mfma(1, 0, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
+    assert lib.adct_compress_mfma(1, 65, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
+    assert lib.adct_compress_mfma(1, 10, None, 1, 64, 64, 64, 4096, None, None, None, None,
+                                  None) == -1
+    assert lib.adct_compress_mfma(1, 10, p, 1, 60, 64, 64, 4096, None, None, None, None, None) == -2
+    assert lib.adct_compress_mfma(1, 10, p, 1, 64, 64, 68, 4096, None, None, None, None, None) == -3
+    assert lib.adct_compress_mfma(1, 10, p, 1, 64, 64, 64, 4096, None, None, C.c_void_p(4100),
+                                  None, None) == -3
+    assert lib.adct_compress_mfma(1, 10, None, 0, 64, 64, 64, 4096, None, None, None, None,
+                                  None) == 0
+
+
 def test_other_entry_points_validate(lib):
     p = C.c_void_p(4096)
     assert lib.adct_fwd2d(1, 8, None, 0, 1, 8, 8, 8, 64, p, None) == -1
