@@ -154,16 +154,26 @@ __global__ __launch_bounds__(64) void compress8_mfma(MfmaParams mp) {
   const v4i zero = {0, 0, 0, 0};
   unsigned long long err = 0;
 
+  // rows 2q, 2q+1 of tile 16 gi + col; the next step's rows are loaded
+  // before the current step is computed, so two steps of loads are in flight
+  auto load_rows = [&](int gi, uint2& a, uint2& b) {
+    a = make_uint2(0x80808080u, 0x80808080u);
+    b = a;
+    if (16 * gi + col < nact) {
+      const int64_t off = row0 + (2 * q) * p.g.pitch + static_cast<int64_t>(tx0 + 16 * gi + col) * 8;
+      a = *reinterpret_cast<const uint2*>(src + off);
+      b = *reinterpret_cast<const uint2*>(src + off + p.g.pitch);
+    }
+  };
+  uint2 n0, n1;
+  load_rows(0, n0, n1);
   for (int gi = 0; gi * 16 < nact; ++gi) {
     const int ng = min(16, nact - 16 * gi);
     const bool active = col < ng;
     const int64_t off0 = row0 + (2 * q) * p.g.pitch + static_cast<int64_t>(tx0 + 16 * gi + col) * 8;
     const int64_t off1 = off0 + p.g.pitch;
-    uint2 r0 = make_uint2(0x80808080u, 0x80808080u), r1 = r0;
-    if (active) {
-      r0 = *reinterpret_cast<const uint2*>(src + off0);
-      r1 = *reinterpret_cast<const uint2*>(src + off1);
-    }
+    const uint2 r0 = n0, r1 = n1;
+    if ((gi + 1) * 16 < nact) load_rows(gi + 1, n0, n1);
     const v4i px = {static_cast<int>(r0.x ^ 0x80808080u), static_cast<int>(r0.y ^ 0x80808080u),
                     static_cast<int>(r1.x ^ 0x80808080u), static_cast<int>(r1.y ^ 0x80808080u)};
     int c[16];
