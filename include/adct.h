@@ -194,8 +194,11 @@ typedef struct {
 typedef struct adct_batch adct_batch_t;
 
 #define ADCT_RUN_BATCHED 0   /* one launch per bucket, covering every image      */
-#define ADCT_RUN_GRAPH 1     /* replay of that sequence captured in a HIP graph  */
+#define ADCT_RUN_GRAPH 1     /* replay of the tuned sequence (per-bucket or     */
+                             /* unified) captured in a HIP graph                */
 #define ADCT_RUN_PER_IMAGE 2 /* one launch per image and bucket (baseline)       */
+#define ADCT_RUN_UNIFIED 3   /* one launch per quantiser class covering every     */
+                             /* bucket, items of all sizes in image/position order */
 
 /* Build a plan (host arrays in, device work list out; allocates device memory
  * and synchronises the device).  dtype is ADCT_U8 or ADCT_I16 for every
@@ -225,11 +228,15 @@ ADCT_API int adct_batch_run(adct_batch_t* plan, const void* d_src, void* d_dst, 
 
 /* Workgroup sizes: bs8 threads (64 or 256) for 8x8 buckets, bs_jam (128 or
  * 256) for 16x16 and 32x32 buckets; a workgroup processes bs8 8x8 TUs or
- * bs_jam / n larger TUs.  adct_batch_tune times both candidates of every
- * bucket on the given buffers (synchronising the stream), keeps the fastest
- * and writes it to chosen[bucket] (chosen may be NULL); when the environment
- * variable ADCT_TUNE_CACHE names a file, choices are cached there keyed by
- * device architecture and bucket shape and reused by later plans. */
+ * bs_jam / n larger TUs (the unified launch always uses 256).
+ * adct_batch_tune times both candidates of every bucket on the given buffers
+ * (synchronising the stream), keeps the fastest and writes it to
+ * chosen[bucket] (chosen may be NULL); it then times the tuned per-bucket
+ * sequence against the unified launch and keeps the faster as the sequence
+ * ADCT_RUN_GRAPH captures (the unified launch until a plan is tuned).  When
+ * the environment variable ADCT_TUNE_CACHE names a file, choices are cached
+ * there keyed by device architecture and plan shape and reused by later
+ * plans. */
 ADCT_API int adct_batch_set_shape(adct_batch_t* plan, int bs8, int bs_jam);
 ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
                              float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen);

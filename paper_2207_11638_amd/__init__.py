@@ -195,7 +195,7 @@ IMAGE_DESC = np.dtype([("src_offset", np.int64), ("dst_offset", np.int64), ("hei
 TU_DESC = np.dtype([("image", np.int32), ("x", np.int32), ("y", np.int32), ("n", np.int32)])
 
 _RUN_MODES = {"batched": _lib.ADCT_RUN_BATCHED, "graph": _lib.ADCT_RUN_GRAPH,
-              "per_image": _lib.ADCT_RUN_PER_IMAGE}
+              "per_image": _lib.ADCT_RUN_PER_IMAGE, "unified": _lib.ADCT_RUN_UNIFIED}
 
 
 class BatchPlan:

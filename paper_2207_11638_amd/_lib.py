@@ -47,7 +47,7 @@ _SIGNATURES = {
     "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp], _i32),
 }
 
-ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE = 0, 1, 2
+ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE, ADCT_RUN_UNIFIED = 0, 1, 2, 3
 
 _lib = None
 

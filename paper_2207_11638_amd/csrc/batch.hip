@@ -80,66 +80,161 @@ __device__ __forceinline__ T* offset_px(T* base, int64_t px, int esize) {
                          : reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + px * esize);
 }
 
-// 8x8 TUs: BS / 64 waves, one TU per thread.
-template <int DT, int KIND, bool QUANT, bool STAGED, int BS>
-__global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
+// Where a launch reads pixels and writes its outputs.
+struct Outs {
+  const BImage* imgs;
+  const int2* pos;        // (x, y) of every TU, sorted
+  const void* src;
+  void* dst;
+  int32_t* kept;
+  float* scaled;
+  unsigned long long* sse;
+};
+
+// One item of 8x8 TUs: BS / 64 waves, one TU per thread.
+template <int DT, int KIND, bool QUANT, bool STAGED, int BS, typename TAB>
+__device__ __forceinline__ void item8(const Outs& o, const BItem& it, const TAB& t, int* S,
+                                      unsigned long long* red) {
   constexpr int RB = STAGED ? kStagedRB : 64;
   constexpr int esize = DT == DT_U8 ? 1 : 2;
-  __shared__ int S[STAGED ? BS * t8::row_stride(kStagedRB) : 1];
-  __shared__ unsigned long long red[BS / 64];
-  const BItem it = p.items[p.item_begin + blockIdx.x];
-  const BImage im = p.imgs[it.image];
+  const BImage im = o.imgs[it.image];
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   t8::WaveIO io;
-  io.src = offset_px(p.src, im.src_off, esize);
-  io.dst = offset_px(p.dst, im.dst_off, esize);
+  io.src = offset_px(o.src, im.src_off, esize);
+  io.dst = offset_px(o.dst, im.dst_off, esize);
   io.pitch = im.pitch;
   io.lane = lane;
   io.nact = min(kWave, max(0, it.count - w * kWave));
   io.active = lane < io.nact;
   int2 xy = make_int2(0, 0);
-  if (io.active) xy = p.pos[it.tu_begin + w * kWave + lane];
+  if (io.active) xy = o.pos[it.tu_begin + w * kWave + lane];
   io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
   const int r = min(im.r, 64);
   io.r = r;
   const int64_t kb = it.kept_base + static_cast<int64_t>(w) * kWave * r;
-  io.kept = p.kept != nullptr ? p.kept + kb : nullptr;
-  io.scaled = p.scaled != nullptr ? p.scaled + kb : nullptr;
-  io.sse = p.sse != nullptr;
+  io.kept = o.kept != nullptr ? o.kept + kb : nullptr;
+  io.scaled = o.scaled != nullptr ? o.scaled + kb : nullptr;
+  io.sse = o.sse != nullptr;
   const unsigned long long e = t8::compress_wave<KIND, DT, RB, QUANT, STAGED, false>(
-      S + (STAGED ? w * kWave * t8::row_stride(RB) : 0), p.t, io);
-  if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
+      S + (STAGED ? w * kWave * t8::row_stride(RB) : 0), t, io);
+  if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
+}
+
+// One item of 16x16 / 32x32 TUs: BS / N tiles.
+template <int DT, int KIND, int N, bool QUANT, int BS, typename TAB>
+__device__ __forceinline__ void item_jam(const Outs& o, const BItem& it, const TAB& t, int* S,
+                                         jam::Shared<N>& sh, unsigned long long* red) {
+  constexpr int esize = DT == DT_U8 ? 1 : 2;
+  using C = jam::Cfg<N, BS>;
+  const BImage im = o.imgs[it.image];
+  jam::load_tables<N, BS>(sh, t, min(im.r, N * N));
+  const int k = threadIdx.x % C::TPW;
+  jam::GroupIO io;
+  io.src = offset_px(o.src, im.src_off, esize);
+  io.dst = offset_px(o.dst, im.dst_off, esize);
+  io.pitch = im.pitch;
+  io.nact = it.count;
+  io.active = k < it.count;
+  int2 xy = make_int2(0, 0);
+  if (io.active) xy = o.pos[it.tu_begin + k];
+  io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
+  const int r = min(im.r, N * N);
+  io.r = r;
+  io.kept = o.kept != nullptr ? o.kept + it.kept_base : nullptr;
+  io.scaled = o.scaled != nullptr ? o.scaled + it.kept_base : nullptr;
+  io.sse = o.sse != nullptr;
+  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false>(S, sh, io);
+  if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
+}
+
+__device__ __forceinline__ Outs outs_of(const BucketParams& p) {
+  return Outs{p.imgs, p.pos, p.src, p.dst, p.kept, p.scaled, p.sse};
+}
+
+// 8x8 TUs: BS / 64 waves, one TU per thread.
+template <int DT, int KIND, bool QUANT, bool STAGED, int BS>
+__global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
+  __shared__ int S[STAGED ? BS * t8::row_stride(kStagedRB) : 1];
+  __shared__ unsigned long long red[BS / 64];
+  const BItem it = p.items[p.item_begin + blockIdx.x];
+  item8<DT, KIND, QUANT, STAGED, BS>(outs_of(p), it, p.t, S, red);
 }
 
 // 16x16 / 32x32 TUs: BS / N tiles per workgroup.
 template <int DT, int KIND, int N, bool QUANT, int BS>
 __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
-  constexpr int esize = DT == DT_U8 ? 1 : 2;
   using C = jam::Cfg<N, BS>;
   __shared__ int S[C::WORDS];
   __shared__ jam::Shared<N> sh;
   __shared__ unsigned long long red[BS / 64];
   const BItem it = p.items[p.item_begin + blockIdx.x];
-  const BImage im = p.imgs[it.image];
-  jam::load_tables<N, BS>(sh, p.t, min(im.r, N * N));
-  const int k = threadIdx.x % C::TPW;
-  jam::GroupIO io;
-  io.src = offset_px(p.src, im.src_off, esize);
-  io.dst = offset_px(p.dst, im.dst_off, esize);
-  io.pitch = im.pitch;
-  io.nact = it.count;
-  io.active = k < it.count;
-  int2 xy = make_int2(0, 0);
-  if (io.active) xy = p.pos[it.tu_begin + k];
-  io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
-  const int r = min(im.r, N * N);
-  io.r = r;
-  io.kept = p.kept != nullptr ? p.kept + it.kept_base : nullptr;
-  io.scaled = p.scaled != nullptr ? p.scaled + it.kept_base : nullptr;
-  io.sse = p.sse != nullptr;
-  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false>(S, sh, io);
-  if (p.sse != nullptr) block_add_sse<BS>(p.sse + it.image, e, red);
+  item_jam<DT, KIND, N, QUANT, BS>(outs_of(p), it, p.t, S, sh, red);
+}
+
+// ------------------------------------------------------------ unified launch
+// All buckets of one quantiser class in one launch of 256-thread workgroups.
+// Item i names its bucket in BItem::pad; the items of all sizes are ordered
+// by image and position, so the TUs of different sizes that share pixel
+// lines are processed at about the same time and those lines are fetched
+// from HBM about once (the other sizes find them in L2 or the shared
+// memory-side cache).  The workgroup branches (uniformly) to the code of its
+// bucket: the same device functions as the per-bucket kernels.
+struct UBucket {
+  int32_t code;       // 0..3: 8x8 staged T1, T2, unstaged T1, T2; 4, 5: 16x16 T1, T2; 6, 7: 32x32
+  int32_t pad[3];
+  Tables t;
+};
+
+struct UnifiedParams {
+  const BImage* imgs;
+  const int2* pos;
+  const void* src;
+  void* dst;
+  int32_t* kept;
+  float* scaled;
+  unsigned long long* sse;
+  const BItem* items;
+  const UBucket* buckets;
+};
+
+constexpr int kUnifiedWords = 256 * 33 > jam::Cfg<32, 256>::WORDS ? 256 * 33
+                                                                  : jam::Cfg<32, 256>::WORDS;
+static_assert(t8::row_stride(kStagedRB) <= 33, "staging stride");
+
+// The dispatcher deals workgroups to the 8 XCDs in turn (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  Workgroup b takes item
+// base(b % 8) + b / 8, so that every XCD walks one contiguous slice of the
+// ordered item list and the neighbouring items that share pixel lines meet
+// in the same L2.  With G = 8 q + m items, XCD x owns q + (x < m) items from
+// base(x) = x q + min(x, m): a bijection of [0, G).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_slice_item(int b, int g) {
+  const int q = g / kXcds, m = g - q * kXcds;
+  const int x = b % kXcds, j = b / kXcds;
+  return x * q + min(x, m) + j;
+}
+
+template <int DT, bool QUANT>
+__global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
+  __shared__ int S[kUnifiedWords];
+  __shared__ jam::Shared<16> sh16;
+  __shared__ jam::Shared<32> sh32;
+  __shared__ unsigned long long red[4];
+  const BItem it = p.items[xcd_slice_item(blockIdx.x, gridDim.x)];
+  const UBucket& b = p.buckets[it.pad];
+  const Outs o{p.imgs, p.pos, p.src, p.dst, p.kept, p.scaled, p.sse};
+  switch (b.code) {
+    case 0: item8<DT, KIND_SIGN, QUANT, true, 256>(o, it, b.t, S, red); break;
+    case 1: item8<DT, KIND_ROUND, QUANT, true, 256>(o, it, b.t, S, red); break;
+    case 2: item8<DT, KIND_SIGN, QUANT, false, 256>(o, it, b.t, S, red); break;
+    case 3: item8<DT, KIND_ROUND, QUANT, false, 256>(o, it, b.t, S, red); break;
+    case 4: item_jam<DT, KIND_SIGN, 16, QUANT, 256>(o, it, b.t, S, sh16, red); break;
+    case 5: item_jam<DT, KIND_ROUND, 16, QUANT, 256>(o, it, b.t, S, sh16, red); break;
+    case 6: item_jam<DT, KIND_SIGN, 32, QUANT, 256>(o, it, b.t, S, sh32, red); break;
+    default: item_jam<DT, KIND_ROUND, 32, QUANT, 256>(o, it, b.t, S, sh32, red); break;
+  }
 }
 
 __global__ void zero_u64(unsigned long long* p, int n) {
@@ -231,6 +326,15 @@ struct adct_batch {
   std::vector<Bucket> buckets;
   BImage* d_imgs = nullptr;
   int2* d_pos = nullptr;
+  // unified launches: one item list per quantiser class (zonal, quantised)
+  struct Unified {
+    bool quant = false;
+    std::vector<BItem> items;
+    BItem* d_items = nullptr;
+  };
+  std::vector<Unified> unified;
+  UBucket* d_ubuckets = nullptr;
+  bool prefer_unified = true;       // the sequence a graph replays (chosen by tune)
   // graph cache
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -258,6 +362,9 @@ void free_plan(adct_batch* b) {
   drop_graph(b);
   for (Bucket& k : b->buckets)
     if (k.d_items) (void)hipFree(k.d_items);
+  for (auto& u : b->unified)
+    if (u.d_items) (void)hipFree(u.d_items);
+  if (b->d_ubuckets) (void)hipFree(b->d_ubuckets);
   if (b->d_imgs) (void)hipFree(b->d_imgs);
   if (b->d_pos) (void)hipFree(b->d_pos);
   delete b;
@@ -300,6 +407,76 @@ hipError_t build_items(adct_batch* b, Bucket& k) {
                    hipMemcpyHostToDevice);
 }
 
+// Items of every bucket for 256-thread workgroups, grouped by quantiser class
+// and ordered by image and by the position of their first TU, plus the
+// device table of bucket codes and constant tables.
+hipError_t build_unified(adct_batch* b, const std::vector<int2>& pos) {
+  std::vector<UBucket> ub(b->buckets.size());
+  for (size_t bi = 0; bi < b->buckets.size(); ++bi) {
+    const Bucket& k = b->buckets[bi];
+    const int code = k.log2n == 3 ? (k.staged ? 0 : 2) : (k.log2n == 4 ? 4 : 6);
+    ub[bi].code = code + (k.kind == KIND_SIGN ? 0 : 1);
+    ub[bi].pad[0] = ub[bi].pad[1] = ub[bi].pad[2] = 0;
+    ub[bi].t = k.tables;
+    const int quant = k.qstep > 0 ? 1 : 0;
+    size_t u = 0;
+    while (u < b->unified.size() && b->unified[u].quant != bool(quant)) ++u;
+    if (u == b->unified.size()) {
+      b->unified.emplace_back();
+      b->unified.back().quant = quant;
+    }
+    const int cap = k.log2n == 3 ? 256 : 256 >> k.log2n;
+    int64_t t = k.tu_begin;
+    while (t < k.tu_end) {
+      const int img = b->tu_image[t];
+      int64_t g = t;
+      while (g < k.tu_end && b->tu_image[g] == img) ++g;
+      for (int64_t s2 = t; s2 < g; s2 += cap) {
+        BItem it;
+        it.image = img;
+        it.tu_begin = static_cast<int32_t>(s2);
+        it.count = static_cast<int32_t>(std::min<int64_t>(cap, g - s2));
+        it.pad = static_cast<int32_t>(bi);
+        it.kept_base = b->tu_kept[s2];
+        b->unified[u].items.push_back(it);
+      }
+      t = g;
+    }
+  }
+  for (auto& u : b->unified) {
+    std::stable_sort(u.items.begin(), u.items.end(), [&](const BItem& x, const BItem& y) {
+      if (x.image != y.image) return x.image < y.image;
+      const int2 px = pos[x.tu_begin], py = pos[y.tu_begin];
+      if (px.y != py.y) return px.y < py.y;
+      return px.x < py.x;
+    });
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&u.d_items),
+                             std::max<size_t>(1, u.items.size()) * sizeof(BItem));
+    if (e == hipSuccess && !u.items.empty())
+      e = hipMemcpy(u.d_items, u.items.data(), u.items.size() * sizeof(BItem),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_ubuckets),
+                           std::max<size_t>(1, ub.size()) * sizeof(UBucket));
+  if (e == hipSuccess && !ub.empty())
+    e = hipMemcpy(b->d_ubuckets, ub.data(), ub.size() * sizeof(UBucket), hipMemcpyHostToDevice);
+  return e;
+}
+
+void launch_unified(const adct_batch* b, const adct_batch::Unified& u, const UnifiedParams& p,
+                    hipStream_t s) {
+  if (u.items.empty()) return;
+  const dim3 grid(static_cast<unsigned>(u.items.size()));
+  if (b->dtype == ADCT_U8) {
+    if (u.quant) bucket_unified<DT_U8, true><<<grid, 256, 0, s>>>(p);
+    else bucket_unified<DT_U8, false><<<grid, 256, 0, s>>>(p);
+  } else {
+    if (u.quant) bucket_unified<DT_I16, true><<<grid, 256, 0, s>>>(p);
+    else bucket_unified<DT_I16, false><<<grid, 256, 0, s>>>(p);
+  }
+}
+
 BucketParams params_for(const adct_batch* b, const Bucket& k, const void* src, void* dst,
                         int32_t* kept, float* scaled, uint64_t* sse) {
   BucketParams p;
@@ -321,6 +498,17 @@ hipError_t enqueue_run(const adct_batch* b, const void* src, void* dst, int32_t*
   const int nb = (b->n_images + 255) / 256;
   auto* sse_dev = reinterpret_cast<unsigned long long*>(sse);
   if (sse != nullptr && nb > 0) zero_u64<<<nb, 256, 0, s>>>(sse_dev, b->n_images);
+  if (mode == ADCT_RUN_UNIFIED) {
+    UnifiedParams up{b->d_imgs, b->d_pos, src, dst, kept, scaled, sse_dev, nullptr,
+                     b->d_ubuckets};
+    for (const auto& u : b->unified) {
+      up.items = u.d_items;
+      launch_unified(b, u, up, s);
+    }
+    if (psnr != nullptr && nb > 0)
+      psnr_kernel<<<nb, 256, 0, s>>>(sse_dev, b->d_imgs, psnr, b->n_images);
+    return hipGetLastError();
+  }
   for (const Bucket& k : b->buckets) {
     const BucketParams p = params_for(b, k, src, dst, kept, scaled, sse);
     if (mode == ADCT_RUN_PER_IMAGE) {
@@ -507,6 +695,7 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
       if (valid_bs(k, cached)) k.bs = cached;
     e = build_items(b, k);
   }
+  if (e == hipSuccess) e = build_unified(b, pos);
   if (e != hipSuccess) {
     free_plan(b);
     return hip_fail(e, "batch: upload");
@@ -557,7 +746,8 @@ ADCT_API int adct_batch_run(adct_batch_t* b, const void* d_src, void* d_dst, int
                             float* d_scaled, uint64_t* d_sse, float* d_psnr, int mode,
                             adct_stream_t stream) {
   if (b == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
-  if (mode != ADCT_RUN_BATCHED && mode != ADCT_RUN_GRAPH && mode != ADCT_RUN_PER_IMAGE)
+  if (mode != ADCT_RUN_BATCHED && mode != ADCT_RUN_GRAPH && mode != ADCT_RUN_PER_IMAGE &&
+      mode != ADCT_RUN_UNIFIED)
     return set_error(ADCT_E_ARG, "batch: bad run mode");
   if (d_psnr != nullptr && d_sse == nullptr)
     return set_error(ADCT_E_ARG, "batch: d_psnr needs d_sse");
@@ -581,7 +771,8 @@ ADCT_API int adct_batch_run(adct_batch_t* b, const void* d_src, void* d_dst, int
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "batch: begin capture");
     const hipError_t le =
-        enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, d_psnr, ADCT_RUN_BATCHED, s);
+        enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, d_psnr,
+                    b->prefer_unified ? ADCT_RUN_UNIFIED : ADCT_RUN_BATCHED, s);
     e = hipStreamEndCapture(s, &b->graph);
     if (le != hipSuccess) return hip_fail(le, "batch: capture launch");
     if (e != hipSuccess) return hip_fail(e, "batch: end capture");
@@ -644,6 +835,34 @@ ADCT_API int adct_batch_tune(adct_batch_t* b, const void* d_src, void* d_dst, in
     e = build_items(b, k);
     if (chosen) chosen[nb] = best_bs;
     ++nb;
+  }
+  // the sequence a graph replays: the tuned per-bucket launches or the
+  // unified launch, whichever is faster on these buffers
+  if (e == hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s:dt%d:tus%lld:img%d:sequence", b->arch.c_str(), b->dtype,
+             static_cast<long long>(b->n_tus), b->n_images);
+    if (const int cached = cache_lookup(buf); cached == 1 || cached == 2) {
+      b->prefer_unified = cached == 1;
+    } else {
+      float best[2] = {1e30f, 1e30f};
+      const int modes[2] = {ADCT_RUN_UNIFIED, ADCT_RUN_BATCHED};
+      for (int m = 0; m < 2 && e == hipSuccess; ++m)
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, nullptr, modes[m], s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) best[m] = std::min(best[m], ms);
+        }
+      if (e == hipSuccess) {
+        b->prefer_unified = best[0] <= best[1];
+        cache_store(buf, b->prefer_unified ? 1 : 2);
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -69,13 +69,14 @@ def run_plan(plan, arena, mode, stream=None):
             sse.cpu().numpy().astype(np.int64), psnr.cpu().numpy())
 
 
+@pytest.mark.parametrize("mode", ["batched", "unified"])
 @pytest.mark.parametrize("kind", ["u8", "i16"])
-def test_batch_matches_oracle_per_tu(kind):
+def test_batch_matches_oracle_per_tu(kind, mode):
     imgs, descs, tus, arena = make_set(kind, 5000 if kind == "u8" else 6000)
     plan = adct.BatchPlan(descs, tus, torch.uint8 if kind == "u8" else torch.int16)
     info = plan.info()
     assert info["tus"] == len(tus) and info["items8"] > 0 and info["items16"] > 0
-    dst, kept, scaled, sse, psnr = run_plan(plan, arena, "batched")
+    dst, kept, scaled, sse, psnr = run_plan(plan, arena, mode)
     want_kept, want_scaled, want_recon, want_sse = oracle_expect(imgs, descs, tus)
     for t in range(len(tus)):
         o = int(plan.tu_kept_offset[t])
@@ -102,7 +103,7 @@ def test_run_modes_and_shapes_agree():
     imgs, descs, tus, arena = make_set("u8", 7000)
     plan = adct.BatchPlan(descs, tus, torch.uint8)
     base = run_plan(plan, arena, "batched")
-    for mode in ("per_image", "batched"):
+    for mode in ("per_image", "batched", "unified"):
         got = run_plan(plan, arena, mode)
         for a, b in zip(base, got):
             assert np.array_equal(a, b)
