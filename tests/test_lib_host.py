@@ -155,3 +155,31 @@ def test_batch_plan_validation_before_gpu(lib):
     assert create(d2, tus) == -3
     assert create(descs, tus, dtype=5) == -1
     assert lib.adct_batch_run(None, None, None, None, None, None, None, 0, None) == -1
+
+
+def test_product_path_never_touches_the_oracle():
+    # the package and its native sources name neither the oracle package nor
+    # any fallback to it; only tests, smoke() and the bench's CPU leg may
+    import ast
+    import pathlib
+    pkg = pathlib.Path(__file__).resolve().parents[1] / "paper_2207_11638_amd"
+    for path in pkg.rglob("*.py"):
+        tree = ast.parse(path.read_text())
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                names = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                names = [node.module or ""]
+            else:
+                continue
+            assert not any(n == "oracle" or n.startswith("oracle.") for n in names), path
+    for path in (pkg / "csrc").iterdir():
+        assert "oracle" not in path.read_text().lower(), path
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    from paper_2207_11638_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing" / "libadct.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        L.load()
