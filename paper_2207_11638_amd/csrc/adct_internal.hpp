@@ -41,6 +41,7 @@ struct PassParams {
   int r;
   int qstep;
   int gpw;                // compress: tile groups per workgroup along a tile row
+  int spread;             // compress, n = 8: images interleaved in dispatch order
   Tables t;
 };
 

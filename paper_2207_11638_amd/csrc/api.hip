@@ -171,6 +171,11 @@ int check_r_q(int n, int r, int qstep) {
 
 int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stream_t stream) {
   if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  // the fused kernels decode their workgroup index in 32 bits
+  const int64_t per = n == 8 ? 64 : 256 / n;
+  if ((p.g.tiles_x + per - 1) / per * static_cast<int64_t>(p.g.tiles_y) * p.g.batch >=
+      (int64_t(1) << 32))
+    return fail(ADCT_E_SHAPE, "image set too large for one launch (2^32 workgroups)");
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int e = n == 8 ? launch_n8(mode, kind, dtype, p, s) : launch_jam(mode, kind, n, dtype, p, s);
   if (e != hipSuccess)

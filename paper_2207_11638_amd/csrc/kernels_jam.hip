@@ -32,15 +32,20 @@ struct WgPos {
 // Tile group gx (TPW tiles from tile column TPW gx) of tile row blockIdx.y of
 // image blockIdx.z.
 template <int N>
-__device__ __forceinline__ WgPos wg_pos(const Geom& g, int gx) {
+__device__ __forceinline__ WgPos wg_pos_at(const Geom& g, int gx, int ty, int img) {
   WgPos w;
   w.tx0 = gx * Cfg<N>::TPW;
-  w.ty = blockIdx.y;
-  w.img = blockIdx.z;
+  w.ty = ty;
+  w.img = img;
   w.tile0 = (static_cast<int64_t>(w.img) * g.tiles_y + w.ty) * g.tiles_x + w.tx0;
   w.pix0 = static_cast<int64_t>(w.img) * g.image_stride +
            static_cast<int64_t>(w.ty) * N * g.pitch + static_cast<int64_t>(w.tx0) * N;
   return w;
+}
+
+template <int N>
+__device__ __forceinline__ WgPos wg_pos(const Geom& g, int gx) {
+  return wg_pos_at<N>(g, gx, blockIdx.y, blockIdx.z);
 }
 
 template <int N>
@@ -70,13 +75,14 @@ __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
   __shared__ Shared<N> sh;
   __shared__ unsigned long long red[kBlock / 64];
   load_tables<N, kBlock>(sh, p.t, p.r);
+  const int img = blockIdx.z, ty = blockIdx.y, wx = blockIdx.x;
   const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
-  const int g0 = blockIdx.x * p.gpw;
+  const int g0 = wx * p.gpw;
   const int g1 = min(g0 + p.gpw, groups_x);
   unsigned long long e = 0;
   for (int gx = g0; gx < g1; ++gx)
-    e += compress_group<KIND, N, DT, QUANT>(S, sh, plain_io<N>(p, wg_pos<N>(p.g, gx)));
-  if (p.sse != nullptr) block_add_sse<kBlock>(p.sse + blockIdx.z, e, red);
+    e += compress_group<KIND, N, DT, QUANT>(S, sh, plain_io<N>(p, wg_pos_at<N>(p.g, gx, ty, img)));
+  if (p.sse != nullptr) block_add_sse<kBlock>(p.sse + img, e, red);
 }
 
 template <int KIND, int N, int DT>

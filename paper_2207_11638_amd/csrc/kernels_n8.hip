@@ -13,6 +13,8 @@
 // The level shift of 8-bit input is folded into the DC coefficient: every AC
 // row of T sums to zero, so T (A - 128) T^T differs from T A T^T only in
 // b[0][0], by 128 N^2.
+#include <algorithm>
+
 #include "tile8.hpp"
 
 namespace adct {
@@ -25,13 +27,14 @@ using namespace t8;
 // RB is a compile-time bound on r: zig-zag positions >= RB are known to be
 // zero, so the compiler drops the arithmetic that only feeds or reads them.
 // One wave covers 64 tiles (4096 pixels) and adds their error energy to the
-// image's total with one atomic.  (Walking several groups per wave, as the
-// 16/32-point kernels do, makes the compiler keep the tables live across the
-// loop and costs more registers than the atomics it saves.)
+// image's total with one atomic; the workgroups interleave p.spread images so
+// that those atomics spread over several addresses.  (Walking several groups per
+// wave, as the 16/32-point kernels do, makes the compiler keep the tables
+// live across the loop and costs more registers than the atomics it saves.)
 template <int KIND, int DT, int RB, bool QUANT>
 __global__ __launch_bounds__(kWave) void compress8(PassParams p) {
   __shared__ int lds[kWave * row_stride(RB)];
-  const WaveTiles w = wave_tiles(p.g, blockIdx.x);
+  const WaveTiles w = wave_tiles_interleaved(p.g, p.spread);
   WaveIO io;
   io.src = p.src;
   io.dst = p.dst;
@@ -146,6 +149,10 @@ template <int KIND, int DT>
 hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
   PassParams p = p_in;
   p.gpw = 1;
+  // images interleaved by the fused kernel: wide for small r, where the
+  // per-workgroup error-energy atomics queue on one address, narrow for large
+  // r, where the output stream wants raster order (measured on the C1 shape)
+  p.spread = std::min(p.g.batch, p.r <= 16 ? 64 : (p.r <= 45 ? 16 : 2));
   const dim3 grid = grid_for(p.g);
   const bool quant = p.qstep > 0;
   switch (mode) {

@@ -218,20 +218,57 @@ struct WaveTiles {
   int64_t pix;     // pixel offset of this thread's tile
 };
 
-// Tiles of group gx (64 tiles from tile column 64 gx) of tile row blockIdx.y
-// of image blockIdx.z.
-__device__ __forceinline__ WaveTiles wave_tiles(const Geom& g, int gx) {
+// Tiles of group gx (64 tiles from tile column 64 gx) of tile row ty of
+// image img.
+__device__ __forceinline__ WaveTiles wave_tiles_at(const Geom& g, int gx, int ty, int img) {
   WaveTiles w;
   w.lane = threadIdx.x;
   const int tx0 = gx * kWave;
   w.tx = tx0 + w.lane;
-  w.img = blockIdx.z;
+  w.img = img;
   w.nact = min(kWave, g.tiles_x - tx0);
   w.active = w.lane < w.nact;
-  w.tile0 = (static_cast<int64_t>(w.img) * g.tiles_y + blockIdx.y) * g.tiles_x + tx0;
+  w.tile0 = (static_cast<int64_t>(w.img) * g.tiles_y + ty) * g.tiles_x + tx0;
   w.pix = static_cast<int64_t>(w.img) * g.image_stride +
-          static_cast<int64_t>(blockIdx.y) * kN * g.pitch + static_cast<int64_t>(w.tx) * kN;
+          static_cast<int64_t>(ty) * kN * g.pitch + static_cast<int64_t>(w.tx) * kN;
   return w;
+}
+
+// Tiles of group gx of tile row blockIdx.y of image blockIdx.z.
+__device__ __forceinline__ WaveTiles wave_tiles(const Geom& g, int gx) {
+  return wave_tiles_at(g, gx, blockIdx.y, blockIdx.z);
+}
+
+// The same tiles with the images interleaved s at a time: the linear
+// workgroup index l of a (groups_x, tiles_y, batch) grid walks the images in
+// blocks of s (the last block holds batch mod s), and inside a block takes
+// image fastest, then group, then tile row; a bijection of the grid.  The
+// workgroups resident at one time then belong to s images, so the one
+// error-energy atomic per workgroup spreads over s addresses, while the
+// workgroups that share a row of an image stay close in dispatch order
+// (their row segments share DRAM pages).  The host picks s: wide where the
+// atomics dominate (small r), narrow where the output stream does.  It
+// keeps every grid below 2^32 workgroups, so 32-bit arithmetic suffices.
+__device__ __forceinline__ WaveTiles wave_tiles_interleaved(const Geom& g, int s) {
+  const uint32_t l = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const uint32_t gxn = gridDim.x;
+  const uint32_t per_image = gxn * static_cast<uint32_t>(g.tiles_y);
+  const uint32_t S = static_cast<uint32_t>(s);
+  const uint32_t full = static_cast<uint32_t>(g.batch) / S;
+  uint32_t blk, within, width;
+  if (l < full * S * per_image) {
+    blk = l / (S * per_image);
+    within = l - blk * S * per_image;
+    width = S;
+  } else {
+    blk = full;
+    within = l - full * S * per_image;
+    width = static_cast<uint32_t>(g.batch) - full * S;
+  }
+  const uint32_t q = within / width;
+  const int img = static_cast<int>(blk * S + (within - q * width));
+  const uint32_t ty = q / gxn;
+  return wave_tiles_at(g, static_cast<int>(q - ty * gxn), static_cast<int>(ty), img);
 }
 
 // ------------------------------------------------------ LDS staged tile words
