@@ -273,32 +273,53 @@ __device__ __forceinline__ WaveTiles wave_tiles_interleaved(const Geom& g, int s
 
 // ------------------------------------------------------ LDS staged tile words
 // Copy the words staged at lds[t * RS + k] (t < nact, k < r) to g[t * r + k].
-// Each pass covers q = 64 / r whole tiles; lane -> (tile lt, word kk) is fixed,
-// so the addresses of every pass differ only by constants.
-template <int R>
+// Pass p stores words 64 p .. 64 p + 63 of the wave's [nact][r] block, one per
+// lane: every pass writes 64 consecutive words, which are two whole 128-byte
+// lines when the block starts on a 256-byte boundary (the plain kernels: a
+// wave's block starts at tile 64 w); NT then selects the streaming hint.
+// When r divides 64 the lane -> (tile, word) map is the same in every pass
+// and the addresses differ only by constants; otherwise the tile and word of
+// each lane step by (64 / r, 64 mod r).
+template <int R, bool NT>
 __device__ __forceinline__ void copy_tiles_out(uint32_t* g, const int* lds, int nact, int lane) {
   constexpr int RS = row_stride(R);
   constexpr int Q = kWave / R;
-  const int lt = lane / R, kk = lane - (lane / R) * R;
-  if (lane >= Q * R) return;
+  if constexpr (Q * R == kWave) {
+    const int lt = lane / R, kk = lane - (lane / R) * R;
 #pragma unroll
-  for (int t0 = 0; t0 < kWave; t0 += Q) {
-    const int t = t0 + lt;
-    if (t < nact) {
-      // a pass stores Q*R consecutive words: the streaming hint pays only when
-      // that is a whole number of cache lines; otherwise L2 merges partial lines
-      if constexpr (Q * R == kWave) st_stream(g + t * R + kk, static_cast<uint32_t>(lds[t * RS + kk]));
-      else g[t * R + kk] = static_cast<uint32_t>(lds[t * RS + kk]);
+    for (int t0 = 0; t0 < kWave; t0 += Q) {
+      const int t = t0 + lt;
+      if (t < nact) st_pix<NT>(g + t * R + kk, static_cast<uint32_t>(lds[t * RS + kk]));
+    }
+  } else {
+    const int total = nact * R;
+#pragma unroll
+    for (int pass = 0; pass < R; ++pass) {   // 64 tiles x R words / 64 lanes
+      const int e = pass * kWave + lane;
+      if (e < total) {
+        const int t = e / R, k = e - (e / R) * R;
+        st_pix<NT>(g + e, static_cast<uint32_t>(lds[t * RS + k]));
+      }
     }
   }
 }
 
+template <bool NT>
 __device__ __forceinline__ void copy_tiles_out_rt(uint32_t* g, const int* lds, int r, int rs,
                                                   int nact, int lane) {
-  const int q = kWave / r;
-  const int lt = lane / r, kk = lane - lt * r;
-  if (lane >= q * r) return;
-  for (int t = lt; t < nact; t += q) g[t * r + kk] = static_cast<uint32_t>(lds[t * rs + kk]);
+  const int total = nact * r;
+  if (lane >= total) return;
+  int t = lane / r, k = lane - (lane / r) * r;
+  const int dt = kWave / r, dk = kWave - dt * r;
+  for (int e = lane; e < total; e += kWave) {
+    st_pix<NT>(g + e, static_cast<uint32_t>(lds[t * rs + k]));
+    t += dt;
+    k += dk;
+    if (k >= r) {
+      k -= r;
+      ++t;
+    }
+  }
 }
 
 // The reverse: g[t * r + k] -> lds[t * RS + k].
@@ -361,8 +382,8 @@ __device__ __forceinline__ unsigned long long compress_wave(int* lds, const TAB&
         }
       __syncthreads();
       uint32_t* g = reinterpret_cast<uint32_t*>(io.scaled);
-      if (r == RB) copy_tiles_out<RB>(g, lds, io.nact, lane);
-      else copy_tiles_out_rt(g, lds, r, RS, io.nact, lane);
+      if (r == RB) copy_tiles_out<RB, NT>(g, lds, io.nact, lane);
+      else copy_tiles_out_rt<NT>(g, lds, r, RS, io.nact, lane);
       __syncthreads();
     } else if (io.active) {
 #pragma unroll
@@ -394,8 +415,8 @@ __device__ __forceinline__ unsigned long long compress_wave(int* lds, const TAB&
         if (k < r) lds[lane * RS + k] = a[kZZ.v[k]][kZZ.u[k]];
       __syncthreads();
       uint32_t* g = reinterpret_cast<uint32_t*>(io.kept);
-      if (r == RB) copy_tiles_out<RB>(g, lds, io.nact, lane);
-      else copy_tiles_out_rt(g, lds, r, RS, io.nact, lane);
+      if (r == RB) copy_tiles_out<RB, NT>(g, lds, io.nact, lane);
+      else copy_tiles_out_rt<NT>(g, lds, r, RS, io.nact, lane);
       __syncthreads();
     } else if (io.active) {
 #pragma unroll
