@@ -94,95 +94,101 @@ struct GroupIO {
 };
 
 // ------------------------------------------------------------- pixel rows
+// One row of one tile as loaded: N/4 words of packed uint8 or N/2 words of
+// packed int16.  The words stay live until the reconstruction is compared
+// with them, which for 8-bit pixels takes three dot-product steps per four
+// pixels.
 template <int N, int DT>
-__device__ __forceinline__ void load_row(const void* src, int64_t off, bool active, int (&x)[N]) {
+struct RowWords {
+  static constexpr int W = DT == DT_U8 ? N / 4 : N / 2;
+  uint32_t w[W];
+};
+
+template <int N, int DT>
+__device__ __forceinline__ void load_row(const void* src, int64_t off, bool active,
+                                         RowWords<N, DT>& rw) {
+  constexpr int V = RowWords<N, DT>::W / 4;  // uint4 per row
+  const uint32_t fill = DT == DT_U8 ? 0x80808080u : 0u;
+  const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(src) +
+                                                  off * (DT == DT_U8 ? 1 : 2));
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    uint4 w = make_uint4(fill, fill, fill, fill);
+    if (active) w = p[q];
+    rw.w[4 * q] = w.x;
+    rw.w[4 * q + 1] = w.y;
+    rw.w[4 * q + 2] = w.z;
+    rw.w[4 * q + 3] = w.w;
+  }
+}
+
+template <int N, int DT>
+__device__ __forceinline__ void unpack_row(const RowWords<N, DT>& rw, int (&x)[N]) {
   if constexpr (DT == DT_U8) {
-    constexpr int V = N / 16;  // uint4 per row
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(src) + off);
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      uint4 w = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
-      if (active) w = p[q];
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    for (int d = 0; d < N / 4; ++d)
 #pragma unroll
-      for (int d = 0; d < 4; ++d)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) x[16 * q + 4 * d + b] = (ws[d] >> (8 * b)) & 0xff;
-    }
+      for (int b = 0; b < 4; ++b) x[4 * d + b] = (rw.w[d] >> (8 * b)) & 0xff;
   } else {
-    constexpr int V = N / 8;
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const int16_t*>(src) + off);
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      uint4 w = make_uint4(0u, 0u, 0u, 0u);
-      if (active) w = p[q];
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        x[8 * q + 2 * d] = static_cast<int>(ws[d] << 16) >> 16;
-        x[8 * q + 2 * d + 1] = static_cast<int>(ws[d]) >> 16;
-      }
+    for (int d = 0; d < N / 2; ++d) {
+      x[2 * d] = static_cast<int>(rw.w[d] << 16) >> 16;
+      x[2 * d + 1] = static_cast<int>(rw.w[d]) >> 16;
     }
   }
 }
 
 // Round z / 2^S half away from zero, clip, store one row; return its squared
-// error against the original row x (when x is given).
+// error against the row as loaded (when x is given).
 template <int N, int DT, int S, bool NT = true>
 __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, bool active,
-                                                        const int (&z)[N], const int* x) {
-  int y[N];
+                                                        const int (&z)[N],
+                                                        const RowWords<N, DT>* x) {
+  RowWords<N, DT> yw;
+  if constexpr (DT == DT_U8) {
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    if constexpr (DT == DT_U8)
-      y[j] = round_shift_u8<S>(z[j]);
-    else
-      y[j] = min(max(round_shift<S>(z[j]), -32768), 32767);
+    for (int d = 0; d < N / 4; ++d) {
+      int y[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) y[b] = round_shift_u8<S>(z[4 * d + b]);
+      yw.w[d] = static_cast<uint32_t>(y[0] | (y[1] << 8) | (y[2] << 16) | (y[3] << 24));
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < N / 2; ++d) {
+      const int y0 = min(max(round_shift<S>(z[2 * d]), -32768), 32767);
+      const int y1 = min(max(round_shift<S>(z[2 * d + 1]), -32768), 32767);
+      yw.w[d] = (static_cast<uint32_t>(y0) & 0xffffu) | (static_cast<uint32_t>(y1) << 16);
+    }
   }
   unsigned long long err = 0;
   if (x != nullptr) {
     if constexpr (DT == DT_U8) {
-      uint32_t acc = 0;
+      // sum (x - y)^2 = sum x^2 + sum y^2 - 2 sum x y; a row's partial sums
+      // stay below 2^21
+      uint32_t sxx = 0, syy = 0, sxy = 0;
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const int d = y[j] - x[j];
-        acc += static_cast<uint32_t>(__mul24(d, d));
+      for (int d = 0; d < N / 4; ++d) {
+        sxx = __builtin_amdgcn_udot4(x->w[d], x->w[d], sxx, false);
+        syy = __builtin_amdgcn_udot4(yw.w[d], yw.w[d], syy, false);
+        sxy = __builtin_amdgcn_udot4(x->w[d], yw.w[d], sxy, false);
       }
-      err = acc;
+      err = sxx + syy - 2u * sxy;
     } else {
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const long long d = y[j] - x[j];
-        err += static_cast<unsigned long long>(d * d);
+      for (int d = 0; d < N / 2; ++d) {
+        const long long d0 = (static_cast<int>(yw.w[d] << 16) >> 16) -
+                             (static_cast<int>(x->w[d] << 16) >> 16);
+        const long long d1 = (static_cast<int>(yw.w[d]) >> 16) - (static_cast<int>(x->w[d]) >> 16);
+        err += static_cast<unsigned long long>(d0 * d0 + d1 * d1);
       }
     }
   }
   if (dst != nullptr && active) {
-    if constexpr (DT == DT_U8) {
-      uint4* p = reinterpret_cast<uint4*>(static_cast<uint8_t*>(dst) + off);
+    uint4* p = reinterpret_cast<uint4*>(static_cast<uint8_t*>(dst) + off * (DT == DT_U8 ? 1 : 2));
 #pragma unroll
-      for (int q = 0; q < N / 16; ++q) {
-        uint32_t ws[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int* yy = y + 16 * q + 4 * d;
-          ws[d] = yy[0] | (yy[1] << 8) | (yy[2] << 16) | (yy[3] << 24);
-        }
-        st_pix<NT>(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
-      }
-    } else {
-      uint4* p = reinterpret_cast<uint4*>(static_cast<int16_t*>(dst) + off);
-#pragma unroll
-      for (int q = 0; q < N / 8; ++q) {
-        uint32_t ws[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int* yy = y + 8 * q + 2 * d;
-          ws[d] = (yy[0] & 0xffff) | (static_cast<uint32_t>(yy[1]) << 16);
-        }
-        st_pix<NT>(p + q, make_uint4(ws[0], ws[1], ws[2], ws[3]));
-      }
-    }
+    for (int q = 0; q < RowWords<N, DT>::W / 4; ++q)
+      st_pix<NT>(p + q, make_uint4(yw.w[4 * q], yw.w[4 * q + 1], yw.w[4 * q + 2], yw.w[4 * q + 3]));
   }
   return err;
 }
@@ -257,14 +263,14 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
 }
 
 // Row forward: load row i of tile k, transform it, store it transposed so that
-// column j of tile k is contiguous: S[k][j][i].  Returns the raw row in x.
+// column j of tile k is contiguous: S[k][j][i].  Returns the row as loaded.
 template <int KIND, int N, int DT, int BS>
-__device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, int k, int (&x)[N]) {
+__device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, int k,
+                                            RowWords<N, DT>& x) {
   using C = Cfg<N, BS>;
   load_row<N, DT>(io.src, io.tile_pix + static_cast<int64_t>(i) * io.pitch, io.active, x);
   int a[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) a[j] = x[j];
+  unpack_row<N, DT>(x, a);
   fwdN<KIND, N>(a);
 #pragma unroll
   for (int j = 0; j < N; ++j) S[k * C::TS + j * C::CS + i] = a[j];
@@ -285,18 +291,26 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   const int k = threadIdx.x % C::TPW;
 
   // phase 1: rows
-  int x[N];
+  RowWords<N, DT> x;
   row_forward<KIND, N, DT, BS>(S, io, a_idx, k, x);
   __syncthreads();
 
-  // phase 2: columns, forward
+  // phase 2: columns, forward.  A column that keeps no coefficient (the
+  // zig-zag prefix keeps rows 0 .. keep-1 of column j) is neither output nor
+  // inverted: its transform is skipped, which whole waves do at small r
+  // (a wave holds 64 / TPW consecutive columns).
   const int j = a_idx;
-  int c[N];
-  read_column<N, BS>(S, j, k, c);
-  fwdN<KIND, N>(c);
-  if constexpr (DT == DT_U8)
-    if (j == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
   const int keep = sh.cnt[j];
+  int c[N];
+  if (keep > 0) {
+    read_column<N, BS>(S, j, k, c);
+    fwdN<KIND, N>(c);
+    if constexpr (DT == DT_U8)
+      if (j == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
+  } else {
+#pragma unroll
+    for (int v = 0; v < N; ++v) c[v] = 0;
+  }
   const int cls_u = sh.cls[j];
   int mq_u[RC.count], dq_u[RC.count];
   if constexpr (QUANT) {
@@ -324,12 +338,14 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
     c[v] = b;
   }
 
-  // phase 2b: columns, inverse
-  invN<KIND, N>(c);
-  if constexpr (QUANT) {
-    // K = 2U: halve exactly so the second pass stays within 32 bits
+  // phase 2b: columns, inverse (a column with nothing kept stays zero)
+  if (keep > 0) {
+    invN<KIND, N>(c);
+    if constexpr (QUANT) {
+      // K = 2U: halve exactly so the second pass stays within 32 bits
 #pragma unroll
-    for (int v = 0; v < N; ++v) c[v] >>= 1;
+      for (int v = 0; v < N; ++v) c[v] >>= 1;
+    }
   }
   write_column_rows<N, BS>(S, j, k, c);
   __syncthreads();
@@ -342,7 +358,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   // zonal: Z = 4 X, y = round(Z / (4 N^2)); quantised: Z = 2 X~, y = round(X~ / (2 N^2))
   const unsigned long long e = store_row<N, DT, C::SROUND, NT>(
       io.dst, io.tile_pix + static_cast<int64_t>(i) * io.pitch, io.active, z,
-      io.sse ? x : nullptr);
+      io.sse ? &x : nullptr);
   __syncthreads();  // S may be reused by the caller
   return io.active ? e : 0ull;
 }

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void forward_jam(PassParams p) {
   const int k = threadIdx.x % C::TPW;
   const GroupIO io = plain_io<N>(p, w);
   const int nact = io.nact;
-  int x[N];
+  RowWords<N, DT> x;
   row_forward<KIND, N, DT, kBlock>(S, io, a_idx, k, x);
   __syncthreads();
   const int j = a_idx;
