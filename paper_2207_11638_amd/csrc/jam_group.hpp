@@ -232,7 +232,9 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
 // layout in S.  Kept values are the coefficients themselves (zonal) or their
 // quantisation levels; scaled values are the coefficients times
 // 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
-template <int N, bool QUANT, int BS>
+// LEVELS: S holds the quantisation levels already (no scaled output), so the
+// kept words are copied as they are.
+template <int N, bool QUANT, bool LEVELS, int BS>
 __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh,
                                                const GroupIO& io) {
   using C = Cfg<N, BS>;
@@ -247,7 +249,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
     const int val = S[k * C::TS + (w & 0xffff)];
     const int ci = w >> 16;
     if (io.kept != nullptr) {
-      const int b = QUANT ? quantise(val, sh.mq[ci]) : val;
+      const int b = QUANT && !LEVELS ? quantise(val, sh.mq[ci]) : val;
       st_stream(reinterpret_cast<uint32_t*>(io.kept) + e, static_cast<uint32_t>(b));
     }
     if (io.scaled != nullptr)
@@ -322,21 +324,32 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   }
   __syncthreads();  // S is free again
 
+  // zonal mask (a prefix of the column) and quantisation levels; when the
+  // scaled values are not wanted the levels themselves are staged for the
+  // outputs, otherwise the coefficients (the gather quantises them again)
+  int lev[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) {
+    const int b = v < keep ? c[v] : 0;
+    lev[v] = QUANT ? quantise(b, mq_u[RC.cls[v]]) : b;
+  }
   if (io.kept != nullptr || io.scaled != nullptr) {
-    write_column_rows<N, BS>(S, j, k, c);   // [k][v][u]
-    __syncthreads();
-    gather_outputs<N, QUANT, BS>(S, sh, io);
+    if (QUANT && io.scaled == nullptr) {
+      write_column_rows<N, BS>(S, j, k, lev);   // [k][v][u]
+      __syncthreads();
+      gather_outputs<N, QUANT, true, BS>(S, sh, io);
+    } else {
+      write_column_rows<N, BS>(S, j, k, c);
+      __syncthreads();
+      gather_outputs<N, QUANT, false, BS>(S, sh, io);
+    }
     __syncthreads();
   }
   if (io.dst == nullptr && !io.sse) return 0ull;
 
-  // zonal mask (a prefix of the column), quantise, dequantise
+  // dequantise
 #pragma unroll
-  for (int v = 0; v < N; ++v) {
-    int b = v < keep ? c[v] : 0;
-    if constexpr (QUANT) b = __mul24(quantise(b, mq_u[RC.cls[v]]), dq_u[RC.cls[v]]);
-    c[v] = b;
-  }
+  for (int v = 0; v < N; ++v) c[v] = QUANT ? __mul24(lev[v], dq_u[RC.cls[v]]) : lev[v];
 
   // phase 2b: columns, inverse (a column with nothing kept stays zero)
   if (keep > 0) {
