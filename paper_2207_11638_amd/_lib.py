@@ -72,7 +72,7 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
-                           "paper_2207_11638_amd.build.build() (or __graft_entry__.build())")
+                           "paper_2207_11638_amd.build.build()")
     lib = C.CDLL(LIB_PATH)
     for name, (args, res) in _SIGNATURES.items():
         fn = getattr(lib, name)
