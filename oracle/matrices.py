@@ -48,7 +48,8 @@ SIZES = (8, 16, 32)
 
 # ---------------------------------------------------------------- section 2
 def dct2_matrix(n: int) -> np.ndarray:
-    """Orthonormal DCT-II, [C]_{m,k} = sqrt(2/N) c_m cos(m(2k+1)pi/(2N))."""
+    """Orthonormal DCT-II, [C]_{m,k} = sqrt(2/N) c_m cos(m(2k+1)pi/(2N)).
+    Section 2: the DCT-II."""
     m = np.arange(n)[:, None]
     k = np.arange(n)[None, :]
     c = np.where(m == 0, 1.0 / math.sqrt(2.0), 1.0)
@@ -56,18 +57,20 @@ def dct2_matrix(n: int) -> np.ndarray:
 
 
 def dct4_matrix(n: int) -> np.ndarray:
-    """Orthonormal DCT-IV, [C]_{m,k} = sqrt(2/N) cos((2m+1)(2k+1)pi/(4N))."""
+    """Orthonormal DCT-IV, [C]_{m,k} = sqrt(2/N) cos((2m+1)(2k+1)pi/(4N)).
+    Section 2: the DCT-IV of the factorization in eq. 2."""
     m = np.arange(n)[:, None]
     k = np.arange(n)[None, :]
     return math.sqrt(2.0 / n) * np.cos((2 * m + 1) * (2 * k + 1) * math.pi / (4 * n))
 
 
 def counter_identity(n: int, dtype=np.int64) -> np.ndarray:
-    """Ibar_n: ones on the anti-diagonal."""
+    """Ibar_n: ones on the anti-diagonal.  Section 2: the counter-identity."""
     return np.fliplr(np.eye(n, dtype=dtype))
 
 
 def _blockdiag(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Direct sum of two blocks (the block-diagonal factors of section 2)."""
     dt = np.result_type(a, b)
     out = np.zeros((a.shape[0] + b.shape[0], a.shape[1] + b.shape[1]), dtype=dt)
     out[: a.shape[0], : a.shape[1]] = a
@@ -76,7 +79,8 @@ def _blockdiag(a: np.ndarray, b: np.ndarray) -> np.ndarray:
 
 
 def _butterfly(n: int, dtype=np.int64) -> np.ndarray:
-    """[[I, Ibar], [Ibar, -I]] of order n (B8, B4 and M_add share this form)."""
+    """[[I, Ibar], [Ibar, -I]] of order n (B8, B4 and M_add share this form).
+    Section 2 (B8 of eq. 1, B4 of eq. 3) and section 6.1 (M_add)."""
     h = n // 2
     eye = np.eye(h, dtype=dtype)
     rev = counter_identity(h, dtype)
@@ -93,10 +97,12 @@ def P8(dtype=np.int64) -> np.ndarray:
 
 
 def B8(dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 1: the butterfly B8."""
     return _butterfly(8, dtype)
 
 
 def P4(dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the permutation P4."""
     perm = [0, 3, 1, 2]
     m = np.zeros((4, 4), dtype=dtype)
     for i, j in enumerate(perm):
@@ -105,6 +111,7 @@ def P4(dtype=np.int64) -> np.ndarray:
 
 
 def B4(dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the butterfly B4."""
     return _butterfly(4, dtype)
 
 
@@ -118,6 +125,7 @@ def Q4(dtype=np.int64) -> np.ndarray:
 
 
 def A1(beta, dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 2: the factor A1, with the parameters beta of section 3."""
     b0, b1, b2, b3 = beta
     return np.array([[b0, 0, 0, b3],
                      [0, b2, b1, 0],
@@ -126,6 +134,7 @@ def A1(beta, dtype=np.int64) -> np.ndarray:
 
 
 def A2(dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 2: the factor A2."""
     return np.array([[1, 1, 0, 0],
                      [1, -1, 0, 0],
                      [0, 0, -1, 1],
@@ -133,6 +142,7 @@ def A2(dtype=np.int64) -> np.ndarray:
 
 
 def A3(alpha, dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 2: the factor A3, with the parameter alpha of section 3."""
     a = alpha
     return np.array([[0, 0, 0, 1],
                      [0, a, a, 0],
@@ -151,23 +161,28 @@ def Ctilde(alpha, gamma, dtype=np.int64) -> np.ndarray:
 
 
 def M1(dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the stage M1."""
     return _blockdiag(np.eye(4, dtype=dtype), counter_identity(4, dtype) @ Q4(dtype))
 
 
 def M2(beta, dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the stage M2 with the parameters beta (section 3)."""
     return _blockdiag(P4(dtype), A1(beta, dtype))
 
 
 def M3(alpha, gamma, dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the stage M3 with the parameters alpha, gamma (section 3)."""
     return _blockdiag(Ctilde(alpha, gamma, dtype), A2(dtype))
 
 
 def M4(alpha, dtype=np.int64) -> np.ndarray:
+    """Section 2, eq. 3: the stage M4 with the parameter alpha (section 3)."""
     return _blockdiag(B4(dtype), A3(alpha, dtype))
 
 
 def chen_map(alpha, beta, gamma, dtype=np.int64) -> np.ndarray:
-    """T_C(alpha, beta, gamma) = P8 M1 M2(beta) M3(alpha, gamma) M4(alpha) B8."""
+    """T_C(alpha, beta, gamma) = P8 M1 M2(beta) M3(alpha, gamma) M4(alpha) B8.
+    Section 3: the parametric map of the factorization in eq. 3."""
     return (P8(dtype) @ M1(dtype) @ M2(beta, dtype) @ M3(alpha, gamma, dtype)
             @ M4(alpha, dtype) @ B8(dtype))
 
@@ -182,6 +197,7 @@ def exact_parameters():
 
 
 def paper_sign(x: float) -> int:
+    """Section 3: the sign() function."""
     return 1 if x > 0 else (-1 if x < 0 else 0)
 
 
@@ -191,7 +207,8 @@ def paper_round(x: float) -> int:
 
 
 def approx_parameters(kind: int):
-    """(alpha, beta, gamma) after applying sign() (kind 1) or round() (kind 2)."""
+    """(alpha, beta, gamma) after applying sign() (kind 1) or round() (kind 2).
+    Section 3: the approximated parameter vectors (round: see the module docstring)."""
     f = paper_sign if kind == SIGN else paper_round
     alpha, beta, gamma = exact_parameters()
     return f(alpha), tuple(f(b) for b in beta), tuple(f(g) for g in gamma)
@@ -205,6 +222,7 @@ def stage_matrices(kind: int):
 
 @lru_cache(maxsize=None)
 def _t8(kind: int) -> np.ndarray:
+    """Section 3, eqs. 4 and 5: the sign-based and round-based 8-point approximations."""
     a, b, g = approx_parameters(kind)
     t = chen_map(a, b, g)
     t.setflags(write=False)
@@ -213,12 +231,14 @@ def _t8(kind: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- section 6
 def m_add(n: int, dtype=np.int64) -> np.ndarray:
-    """M_add_N = [[I, Ibar], [Ibar, -I]] (N additions)."""
+    """M_add_N = [[I, Ibar], [Ibar, -I]] (N additions).
+    Section 6.1: M_add of the JAM recursion."""
     return _butterfly(n, dtype)
 
 
 def m_per(n: int, dtype=np.int64) -> np.ndarray:
-    """M_per_N: output 2k takes input k, output 2k+1 takes input N/2 + k."""
+    """M_per_N: output 2k takes input k, output 2k+1 takes input N/2 + k.
+    Section 6.1: M_per of the JAM recursion (read as the interleave)."""
     m = np.zeros((n, n), dtype=dtype)
     h = n // 2
     for k in range(h):
@@ -259,7 +279,8 @@ def jam_factors(kind: int, n: int):
 # ---------------------------------------------------------- exact inverses
 def fraction_inverse(m) -> list:
     """Exact inverse of a square integer/rational matrix (Gauss-Jordan on
-    Fractions).  Returns a list of lists of Fraction; raises on singular input."""
+    Fractions).  Returns a list of lists of Fraction; raises on singular input.
+    Exact rational inversion, used for the inverses of sections 3 and 6.1."""
     n = len(m)
     a = [[Fraction(int(m[i][j])) if not isinstance(m[i][j], Fraction) else m[i][j]
           for j in range(n)] + [Fraction(int(i == j)) for j in range(n)]
@@ -283,6 +304,7 @@ def scaled_inverse(kind: int, n: int) -> np.ndarray:
     """U_N = N * T_N^-1 as int64 (read-only).
 
     Computed by exact rational inversion; raises if N*T_N^-1 is not integral.
+    Sections 3 (eqs. 6, 7) and 6.1: the exact inverse, scaled to integers.
     """
     inv = fraction_inverse(transform_matrix(kind, n).tolist())
     u = np.zeros((n, n), dtype=np.int64)
@@ -298,18 +320,19 @@ def scaled_inverse(kind: int, n: int) -> np.ndarray:
 
 # ------------------------------------------------------------ section 3.1
 def diag_ttt(kind: int, n: int) -> np.ndarray:
-    """diag(T_N T_N^T) as int64."""
+    """diag(T_N T_N^T) as int64.  Section 3.1: the diagonal of T T^T."""
     t = transform_matrix(kind, n)
     return np.einsum("ij,ij->i", t, t)
 
 
 def scale_vector(kind: int, n: int) -> np.ndarray:
-    """s = diag(S') = 1/sqrt(diag(T T^T)) in float64."""
+    """s = diag(S') = 1/sqrt(diag(T T^T)) in float64.
+    Section 3.1: the orthogonalising diagonal S'."""
     return 1.0 / np.sqrt(diag_ttt(kind, n).astype(np.float64))
 
 
 def near_orthogonal(kind: int, n: int) -> np.ndarray:
-    """C = S' T (float64)."""
+    """C = S' T (float64).  Section 3.1: the near-orthogonal approximation."""
     return scale_vector(kind, n)[:, None] * transform_matrix(kind, n).astype(np.float64)
 
 
@@ -322,6 +345,7 @@ def zigzag(n: int) -> tuple:
     Anti-diagonal d = v + u is visited in increasing order; on odd d the scan
     runs from (0, d) towards increasing v, on even d from (d, 0) towards
     decreasing v; positions outside the square are skipped.
+    Section 5.1: the zig-zag order of the retained coefficients.
     """
     order = []
     for d in range(2 * n - 1):

@@ -25,16 +25,19 @@ import numpy as np
 
 
 def deviation_from_diagonality(m: np.ndarray) -> float:
+    """Section 3.1: the deviation from diagonality."""
     m = np.asarray(m, dtype=np.float64)
     return 1.0 - float(np.sum(np.diag(m) ** 2)) / float(np.sum(m * m))
 
 
 def total_error_energy(c_exact: np.ndarray, c_approx: np.ndarray) -> float:
+    """Section 4.1: the total error energy (Table 1)."""
     d = np.asarray(c_exact, np.float64) - np.asarray(c_approx, np.float64)
     return math.pi * float(np.sum(d * d))
 
 
 def ar1_covariance(n: int, rho: float) -> np.ndarray:
+    """Section 4.1: the first-order Markov model."""
     idx = np.arange(n)
     return rho ** np.abs(idx[:, None] - idx[None, :]).astype(np.float64)
 
@@ -44,6 +47,7 @@ def coding_gain(c: np.ndarray, rho: float, basis: str = "rows") -> float:
 
     A_k = su[(h_k^T h_k) o R_x] with h_k the k-th row of C; B_k = ||g_k||^2
     with g_k the k-th row (basis="rows") or column (basis="cols") of C^-1.
+    Section 4.1: the coding gain.
     """
     c = np.asarray(c, dtype=np.float64)
     n = c.shape[0]
@@ -60,7 +64,7 @@ def coding_gain(c: np.ndarray, rho: float, basis: str = "rows") -> float:
 
 
 def klt_coding_gain(n: int, rho: float) -> float:
-    """Coding gain of the KLT: the eigenvalues of R_x are its subband variances."""
+    """Coding gain of the KLT: the eigenvalues of R_x are its subband variances.  Section 4.1."""
     lam = np.linalg.eigvalsh(ar1_covariance(n, rho))
     return -10.0 * float(np.mean(np.log10(lam)))
 
@@ -68,10 +72,12 @@ def klt_coding_gain(n: int, rho: float) -> float:
 def additions_of_factor(m: np.ndarray) -> int:
     """Additions needed to apply a sparse factor whose non-zero entries are
     +-1 or powers of two: each output row with k non-zeros costs k - 1 additions
-    (sign changes and power-of-two scalings are free)."""
+    (sign changes and power-of-two scalings are free).
+    Section 4.2: addition counts (Tables 2 and 4)."""
     m = np.asarray(m)
     return int(sum(max(int(np.count_nonzero(row)) - 1, 0) for row in m))
 
 
 def additions_of_chain(factors) -> int:
+    """Section 4.2: addition counts (Tables 2 and 4)."""
     return sum(additions_of_factor(f) for f in factors)

@@ -50,20 +50,22 @@ QUANT_FRAC = 1            # fractional bits carried by the dequantised coefficie
 
 def round_half_away_div(p: np.ndarray, q: int) -> np.ndarray:
     """round(p / q) for integer p and positive integer q, with the paper's
-    round() (half away from zero), in exact integer arithmetic."""
+    round() (half away from zero), in exact integer arithmetic.
+    Section 3: the paper's round()."""
     p = np.asarray(p, dtype=np.int64)
     mag = (2 * np.abs(p) + q) // (2 * q)
     return np.where(p < 0, -mag, mag)
 
 
 def round_half_away_float(x: np.ndarray) -> np.ndarray:
-    """The paper's round(x) = sign(x) floor(|x| + 1/2) on float64 values."""
+    """The paper's round(x) = sign(x) floor(|x| + 1/2) on float64 values.  Section 3."""
     x = np.asarray(x, dtype=np.float64)
     return np.sign(x) * np.floor(np.abs(x) + 0.5)
 
 
 def to_tiles(img: np.ndarray, n: int) -> np.ndarray:
-    """(H, W) -> (H/N, W/N, N, N); tile (by, bx) covers rows by*N.., cols bx*N.."""
+    """(H, W) -> (H/N, W/N, N, N); tile (by, bx) covers rows by*N.., cols bx*N..
+    Section 5.1: the non-overlapping N x N blocks."""
     h, w = img.shape
     if h % n or w % n:
         raise ValueError(f"image {h}x{w} is not a multiple of N={n}")
@@ -71,12 +73,14 @@ def to_tiles(img: np.ndarray, n: int) -> np.ndarray:
 
 
 def from_tiles(t: np.ndarray) -> np.ndarray:
+    """Section 5.1: blocks back to the image."""
     th, tw, n, _ = t.shape
     return t.transpose(0, 2, 1, 3).reshape(th * n, tw * n)
 
 
 def level_shift(img: np.ndarray) -> np.ndarray:
-    """uint8 pixels -> pixel - 128 (int64); int16 residuals unchanged."""
+    """uint8 pixels -> pixel - 128 (int64); int16 residuals unchanged.
+    Section 5.1 (JPEG-like compression; the JPEG level shift)."""
     if img.dtype == np.uint8:
         return img.astype(np.int64) - 128
     if img.dtype == np.int16:
@@ -85,7 +89,8 @@ def level_shift(img: np.ndarray) -> np.ndarray:
 
 
 def forward2d(img: np.ndarray, kind: int, n: int) -> np.ndarray:
-    """b = T A T^T for every tile; returns int64 (H/N, W/N, N, N)."""
+    """b = T A T^T for every tile; returns int64 (H/N, W/N, N, N).
+    Section 5.1: the 2D transform of each block."""
     t = transform_matrix(kind, n)
     a = to_tiles(level_shift(img), n)
     return t @ a @ t.T
@@ -99,7 +104,7 @@ def forward2d_paper_literal(img: np.ndarray, kind: int, n: int) -> np.ndarray:
 
 
 def zigzag_mask(n: int, r: int) -> np.ndarray:
-    """Boolean (N, N) mask of the first r zig-zag positions."""
+    """Boolean (N, N) mask of the first r zig-zag positions.  Section 5.1: zonal retention."""
     if not 0 <= r <= n * n:
         raise ValueError("r out of range")
     m = np.zeros((n, n), dtype=bool)
@@ -109,7 +114,8 @@ def zigzag_mask(n: int, r: int) -> np.ndarray:
 
 
 def zigzag_gather(b: np.ndarray, r: int) -> np.ndarray:
-    """First r coefficients of each tile in zig-zag order: (..., r)."""
+    """First r coefficients of each tile in zig-zag order: (..., r).
+    Section 5.1: zonal retention."""
     n = b.shape[-1]
     zz = zigzag(n)[:r]
     vs = np.array([v for v, _ in zz], dtype=np.int64)
@@ -118,7 +124,8 @@ def zigzag_gather(b: np.ndarray, r: int) -> np.ndarray:
 
 
 def zigzag_scatter(kept: np.ndarray, n: int) -> np.ndarray:
-    """Inverse of ``zigzag_gather``: zero-filled (..., N, N) tiles."""
+    """Inverse of ``zigzag_gather``: zero-filled (..., N, N) tiles.
+    Section 5.1: zonal retention."""
     r = kept.shape[-1]
     out = np.zeros(kept.shape[:-1] + (n, n), dtype=kept.dtype)
     for i, (v, u) in enumerate(zigzag(n)[:r]):
@@ -134,7 +141,8 @@ def retain(b: np.ndarray, r: int) -> np.ndarray:
 
 
 def scaled_coefficients(b: np.ndarray, kind: int, n: int) -> np.ndarray:
-    """c_vu = s_v s_u b_vu: coefficients of the near-orthogonal C = S' T, float64."""
+    """c_vu = s_v s_u b_vu: coefficients of the near-orthogonal C = S' T, float64.
+    Section 3.1: the orthogonalising scale."""
     s = scale_vector(kind, n)
     return np.outer(s, s) * b.astype(np.float64)
 
@@ -149,13 +157,16 @@ def quant_tables(kind: int, n: int, qstep: int):
 
 
 def quantise(b: np.ndarray, mq: np.ndarray) -> np.ndarray:
-    """level = sign(b) * floor(|b| MQ / 2^24 + 1/2)  (int64)."""
+    """level = sign(b) * floor(|b| MQ / 2^24 + 1/2)  (int64).
+    Section 3.1 lets S be absorbed in a quantiser; this one is the project's own (parity
+    unpinned against the paper)."""
     b = np.asarray(b, dtype=np.int64)
     mag = (np.abs(b) * mq + (1 << (QUANT_SHIFT - 1))) >> QUANT_SHIFT
     return np.where(b < 0, -mag, mag)
 
 
 def dequantise(level: np.ndarray, dq: np.ndarray) -> np.ndarray:
+    """The inverse step of ``quantise`` (section 3.1; parity unpinned against the paper)."""
     return np.asarray(level, dtype=np.int64) * dq
 
 
@@ -164,6 +175,7 @@ def inverse2d(b: np.ndarray, kind: int, n: int, out_dtype, frac_bits: int = 0) -
 
     X = U b U^T with U = N T^-1, y = round(X / (2^frac_bits N^2)); 8-bit output
     adds 128 and clips to [0, 255], 16-bit output saturates.
+    Section 5.1 with the exact inverse of sections 3 and 6.1.
     """
     u = scaled_inverse(kind, n)
     x = u @ np.asarray(b, dtype=np.int64) @ u.T
@@ -176,12 +188,14 @@ def inverse2d(b: np.ndarray, kind: int, n: int, out_dtype, frac_bits: int = 0) -
 
 
 def sse(a: np.ndarray, b: np.ndarray) -> int:
+    """Section 5.1: the squared error behind the PSNR."""
     d = a.astype(np.int64) - b.astype(np.int64)
     return int(np.sum(d * d))
 
 
 def psnr(sse_value: int, num_pixels: int, peak: float = 255.0) -> float:
-    """PSNR = 10 log10(peak^2 / MSE) in float64; +inf when SSE = 0."""
+    """PSNR = 10 log10(peak^2 / MSE) in float64; +inf when SSE = 0.
+    Section 5.1: quality measured by PSNR."""
     if sse_value == 0:
         return math.inf
     mse = sse_value / float(num_pixels)
@@ -201,6 +215,7 @@ def compress(img: np.ndarray, kind: int, n: int, r: int, qstep: int = 0) -> dict
       ``recon``  reconstruction, same dtype and shape as ``img``
       ``sse``    exact sum of squared reconstruction errors
       ``psnr``   float64
+    Section 5.1: the JPEG-like experiment for one image.
     """
     b = forward2d(img, kind, n)
     scaled = zigzag_gather(scaled_coefficients(b, kind, n), r)
