@@ -70,7 +70,9 @@ typedef void* adct_stream_t;
 /* Library version (integer, increases with every ABI change). */
 ADCT_API int adct_version(void);
 
-/* Text of the last error on the calling thread ("" if none). */
+/* Text of the last error on the calling thread ("" if none); library
+ * bookkeeping, no operation of the paper.  The string is owned by the
+ * library and valid until the thread's next call. */
 ADCT_API const char* adct_last_error(void);
 
 /* ----------------------------------------------------------------------
@@ -84,8 +86,10 @@ ADCT_API const char* adct_last_error(void);
  * factorization of section 6.1), from the inverse butterfly.  */
 ADCT_API int adct_get_matrix(int transform, int n, int inverse, int32_t* host_out);
 
-/* JPEG zig-zag scan of an n x n block: host_out[k] = v * n + u of the k-th
- * scanned coefficient (n*n entries). */
+/* The zig-zag scan of section 5.1 (the JPEG rule, generalised to n x n by
+ * anti-diagonals): host_out[k] = v * n + u of the k-th scanned coefficient
+ * (n*n entries, caller-owned host memory).  ADCT_E_ARG for a bad n or a null
+ * pointer. */
 ADCT_API int adct_zigzag(int n, int32_t* host_out);
 
 /* s_k = 1 / sqrt((T_N T_N^T)_kk), the diagonal of S' (section 3.1), in double
@@ -139,7 +143,8 @@ ADCT_API int adct_compress(int transform, int n, int r, int qstep, const void* d
                            int64_t image_stride, int32_t* d_kept, float* d_scaled,
                            void* d_recon, uint64_t* d_sse, adct_stream_t stream);
 
-/* Inverse of the compressed form: d_kept is int32 [tiles][r] as adct_compress
+/* Inverse of the compressed form (section 5.1 with the exact inverse of
+ * eqs. 6/7 and section 6.1): d_kept is int32 [tiles][r] as adct_compress
  * writes it (coefficients or, with qstep > 0, levels).  Writes the
  * reconstruction to d_dst; the result equals adct_compress's d_recon. */
 ADCT_API int adct_decompress(int transform, int n, int r, int qstep, const int32_t* d_kept,
@@ -212,9 +217,12 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
                                int64_t* tu_kept_offset, int64_t* kept_words,
                                adct_batch_t** plan);
 
+/* Free a plan and its device work lists (bookkeeping; waits for nothing, so
+ * the caller must not destroy a plan whose runs are still queued). */
 ADCT_API int adct_batch_destroy(adct_batch_t* plan);
 
-/* Run the plan.  d_src/d_dst are pixel arenas addressed by the image
+/* Run the plan: every TU goes through the pipeline of adct_compress
+ * (section 5.1 with the transforms of eqs. 4/5 and section 6.1).  d_src/d_dst are pixel arenas addressed by the image
  * descriptors (16-byte aligned); d_kept/d_scaled hold kept_words int32/float
  * words; d_sse and d_psnr hold one uint64/float per image.  d_sse is
  * overwritten with the error energy of this run and d_psnr receives
@@ -226,7 +234,9 @@ ADCT_API int adct_batch_run(adct_batch_t* plan, const void* d_src, void* d_dst, 
                             float* d_scaled, uint64_t* d_sse, float* d_psnr, int mode,
                             adct_stream_t stream);
 
-/* Workgroup sizes: bs8 threads (64 or 256) for 8x8 buckets, bs_jam (128 or
+/* Launch shape of the plan and its tuning (no operation of the paper).
+ * Workgroup sizes:
+ * bs8 threads (64 or 256) for 8x8 buckets, bs_jam (128 or
  * 256) for 16x16 and 32x32 buckets; a workgroup processes bs8 8x8 TUs or
  * bs_jam / n larger TUs (the unified launch always uses 256).
  * adct_batch_tune times both candidates of every bucket on the given buffers
@@ -241,14 +251,15 @@ ADCT_API int adct_batch_set_shape(adct_batch_t* plan, int bs8, int bs_jam);
 ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
                              float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen);
 
-/* Work-list statistics: out[0..7] = images, TUs, work items, items of size
- * 8, 16 and 32, buckets, compute units of the device. */
+/* Work-list statistics (bookkeeping): out[0..7] = images, TUs, work items,
+ * items of size 8, 16 and 32, buckets, compute units of the device. */
 ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
 
 /* ----------------------------------------------------------------------
  * Serving: continuous batching of independent compress requests.
  *
- * Each request is one image compressed with the fused pipeline of
+ * Each request is one image compressed with the fused pipeline (section 5.1;
+ * eqs. 4/5 and section 6.1) of
  * adct_compress (its own transform, n, r, qstep and dtype).  A server admits
  * requests against an HBM budget, queues them, and launches whatever is
  * queued as one batch whenever one of its max_inflight batch slots is free:
@@ -311,19 +322,22 @@ typedef struct {
 ADCT_API int adct_server_create(int64_t budget_bytes, int max_inflight, int max_batch,
                                 adct_stream_t stream, adct_server_t** server);
 
-/* Wait for every launched batch, then free the server and its arena. */
+/* Wait for every launched batch, then free the server and its arena
+ * (bookkeeping). */
 ADCT_API int adct_server_destroy(adct_server_t* server);
 
-/* Validate and admit one request (host only).  ADCT_OK: queued.
+/* Validate and admit one request (admission bookkeeping, host only; the
+ * request is copied, its buffers stay caller-owned).  ADCT_OK: queued.
  * ADCT_E_BUDGET: not admitted now (or never, if it exceeds the budget). */
 ADCT_API int adct_server_submit(adct_server_t* server, const adct_request_t* request);
 
 /* Launch the queued requests (at most max_batch, oldest first) as one batch
- * if a batch slot is free; *launched receives the number of requests
+ * if a batch slot is free: each request runs the pipeline of adct_compress
+ * (section 5.1); *launched receives the number of requests
  * launched (0 when nothing is queued or every slot is busy). */
 ADCT_API int adct_server_flush(adct_server_t* server, int* launched);
 
-/* Report completed batches (in launch order among those complete) as long as
+/* Report completed batches (bookkeeping; in launch order among those complete) as long as
  * their requests fit in out[0 .. max_out) (max_out must be at least
  * max_batch).  wait != 0 blocks
  * until every launched batch has completed.  Arena space of the batches
@@ -331,17 +345,19 @@ ADCT_API int adct_server_flush(adct_server_t* server, int* launched);
 ADCT_API int adct_server_poll(adct_server_t* server, int wait, adct_completion_t* out,
                               int max_out, int* n_out);
 
-/* out[0..7] = submitted, completed, batches launched, queued, in flight,
- * bytes charged, largest batch, ADCT_E_BUDGET refusals. */
+/* Statistics (bookkeeping): out[0..7] = submitted, completed, batches
+ * launched, queued, in flight, bytes charged, largest batch, ADCT_E_BUDGET
+ * refusals. */
 ADCT_API int adct_server_stats(const adct_server_t* server, int64_t* out);
 
-/* Milliseconds on the server clock. */
+/* Milliseconds on the server clock (bookkeeping; 0 for a null server). */
 ADCT_API double adct_server_clock_ms(const adct_server_t* server);
 
 /* Replay an arrival trace in real time on the calling thread: request i
  * arrives arrival_ms[i] milliseconds after the start (non-decreasing), is
  * admitted in arrival order (waiting while the budget is full), batched and
- * launched; the call returns when every request has completed.
+ * launched through the pipeline of adct_compress (section 5.1); the call
+ * returns when every request has completed.
  * latency_ms[i] = completion - arrival, batch_of[i] = its batch, sse[i] = its
  * error energy (any of the three may be NULL).  A request that fails
  * validation gets latency NaN and batch -1.  The server must be idle. */
