@@ -222,8 +222,8 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
 ADCT_API int adct_batch_destroy(adct_batch_t* plan);
 
 /* Run the plan: every TU goes through the pipeline of adct_compress
- * (section 5.1 with the transforms of eqs. 4/5 and section 6.1).  d_src/d_dst are pixel arenas addressed by the image
- * descriptors (16-byte aligned); d_kept/d_scaled hold kept_words int32/float
+ * (section 5.1 with the transforms of eqs. 4/5 and section 6.1).  d_src /
+ * d_dst are pixel arenas addressed by the image descriptors (16-byte aligned); d_kept/d_scaled hold kept_words int32/float
  * words; d_sse and d_psnr hold one uint64/float per image.  d_sse is
  * overwritten with the error energy of this run and d_psnr receives
  * 10 log10(255^2 H W / sse) (+inf when sse = 0) in single precision.  Any
@@ -337,9 +337,9 @@ ADCT_API int adct_server_submit(adct_server_t* server, const adct_request_t* req
  * launched (0 when nothing is queued or every slot is busy). */
 ADCT_API int adct_server_flush(adct_server_t* server, int* launched);
 
-/* Report completed batches (bookkeeping; in launch order among those complete) as long as
- * their requests fit in out[0 .. max_out) (max_out must be at least
- * max_batch).  wait != 0 blocks
+/* Report completed batches (bookkeeping; in launch order among those
+ * complete) as long as their requests fit in out[0 .. max_out) (max_out must
+ * be at least max_batch).  wait != 0 blocks
  * until every launched batch has completed.  Arena space of the batches
  * reported by the previous poll is released first. */
 ADCT_API int adct_server_poll(adct_server_t* server, int wait, adct_completion_t* out,
