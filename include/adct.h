@@ -221,15 +221,15 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
  * the caller must not destroy a plan whose runs are still queued). */
 ADCT_API int adct_batch_destroy(adct_batch_t* plan);
 
-/* Run the plan: every TU goes through the pipeline of adct_compress
- * (section 5.1 with the transforms of eqs. 4/5 and section 6.1).  d_src /
- * d_dst are pixel arenas addressed by the image descriptors (16-byte
- * aligned); d_kept/d_scaled hold kept_words int32/float words; d_sse and d_psnr hold one uint64/float per image.  d_sse is
- * overwritten with the error energy of this run and d_psnr receives
- * 10 log10(255^2 H W / sse) (+inf when sse = 0) in single precision.  Any
- * output may be NULL, except that d_psnr needs d_sse.  mode is one of
- * ADCT_RUN_*; ADCT_RUN_GRAPH needs a non-null stream and re-captures only
- * when a buffer or the stream changes. */
+/* Run the plan: every TU goes through the pipeline of adct_compress (section
+ * 5.1 with the transforms of eqs. 4/5 and section 6.1).  d_src / d_dst are
+ * pixel arenas addressed by the image descriptors (16-byte aligned);
+ * d_kept/d_scaled hold kept_words int32/float words; d_sse and d_psnr hold one
+ * uint64/float per image.  d_sse is overwritten with the error energy of this
+ * run and d_psnr receives 10 log10(255^2 H W / sse) (+inf when sse = 0) in
+ * single precision.  Any output may be NULL, except that d_psnr needs d_sse.
+ * mode is one of ADCT_RUN_*; ADCT_RUN_GRAPH needs a non-null stream and re-
+ * captures only when a buffer or the stream changes. */
 ADCT_API int adct_batch_run(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
                             float* d_scaled, uint64_t* d_sse, float* d_psnr, int mode,
                             adct_stream_t stream);
