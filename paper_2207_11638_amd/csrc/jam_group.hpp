@@ -207,18 +207,19 @@ __device__ __forceinline__ void read_column(const int* S, int j, int k, int (&c)
   for (int v = 0; v < N; ++v) c[v] = S[k * C::TS + j * C::CS + v];
 }
 
-template <int N, int BS>
+template <int N, int BS, int ROWS = N>
 __device__ __forceinline__ void write_column_rows(int* S, int j, int k, const int (&c)[N]) {
   using C = Cfg<N, BS>;
 #pragma unroll
-  for (int v = 0; v < N; ++v) S[k * C::TS + v * C::CS + j] = c[v];
+  for (int v = 0; v < ROWS; ++v) S[k * C::TS + v * C::CS + j] = c[v];
 }
 
-template <int N, int BS>
+// Row i of tile k; entries u >= COLS are zero and not read.
+template <int N, int BS, int COLS = N>
 __device__ __forceinline__ void read_row(const int* S, int i, int k, int (&z)[N]) {
   using C = Cfg<N, BS>;
 #pragma unroll
-  for (int u = 0; u < N; ++u) z[u] = S[k * C::TS + i * C::CS + u];
+  for (int u = 0; u < N; ++u) z[u] = u < COLS ? S[k * C::TS + i * C::CS + u] : 0;
 }
 
 // Copy ``count`` contiguous words from LDS to global memory (all threads).
@@ -266,7 +267,9 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
 
 // Row forward: load row i of tile k, transform it, store it transposed so that
 // column j of tile k is contiguous: S[k][j][i].  Returns the row as loaded.
-template <int KIND, int N, int DT, int BS>
+// Only columns j < KB are stored (the kept bound: no column >= KB keeps a
+// coefficient), so the butterfly's other outputs are dead code.
+template <int KIND, int N, int DT, int BS, int KB = N>
 __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, int k,
                                             RowWords<N, DT>& x) {
   using C = Cfg<N, BS>;
@@ -275,7 +278,7 @@ __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, in
   unpack_row<N, DT>(x, a);
   fwdN<KIND, N>(a);
 #pragma unroll
-  for (int j = 0; j < N; ++j) S[k * C::TS + j * C::CS + i] = a[j];
+  for (int j = 0; j < KB; ++j) S[k * C::TS + j * C::CS + i] = a[j];
 }
 
 // ------------------------------------------------------------ fused group
@@ -284,8 +287,12 @@ __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, in
 // reconstruction error (its row of its tile; 0 unless io.sse is set and the
 // tile exists).  Every thread of the workgroup calls it; the tables in sh
 // must have been written before it is called.  NT selects non-temporal
-// reconstruction stores.
-template <int KIND, int N, int DT, bool QUANT, int BS = kBlock, bool NT = true>
+// reconstruction stores.  KB is a compile-time kept bound: every retained
+// coefficient has v, u < KB (true when r <= KB (KB + 1) / 2, the zig-zag
+// prefix of KB anti-diagonals), so the forward butterflies need only their
+// first KB outputs and the inverse ones see zeros in their inputs >= KB; the
+// compiler removes the additions that only feed or read those.
+template <int KIND, int N, int DT, bool QUANT, int BS = kBlock, bool NT = true, int KB = N>
 __device__ __forceinline__ unsigned long long compress_group(int* S, const Shared<N>& sh, const GroupIO& io) {
   using C = Cfg<N, BS>;
   constexpr RowClasses<N> RC = row_classes<KIND, N>();
@@ -294,7 +301,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
 
   // phase 1: rows
   RowWords<N, DT> x;
-  row_forward<KIND, N, DT, BS>(S, io, a_idx, k, x);
+  row_forward<KIND, N, DT, BS, KB>(S, io, a_idx, k, x);
   __syncthreads();
 
   // phase 2: columns, forward.  A column that keeps no coefficient (the
@@ -330,16 +337,16 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   int lev[N];
 #pragma unroll
   for (int v = 0; v < N; ++v) {
-    const int b = v < keep ? c[v] : 0;
+    const int b = v < KB && v < keep ? c[v] : 0;
     lev[v] = QUANT ? quantise(b, mq_u[RC.cls[v]]) : b;
   }
   if (io.kept != nullptr || io.scaled != nullptr) {
     if (QUANT && io.scaled == nullptr) {
-      write_column_rows<N, BS>(S, j, k, lev);   // [k][v][u]
+      write_column_rows<N, BS, KB>(S, j, k, lev);   // [k][v][u], rows v < KB
       __syncthreads();
       gather_outputs<N, QUANT, true, BS>(S, sh, io);
     } else {
-      write_column_rows<N, BS>(S, j, k, c);
+      write_column_rows<N, BS, KB>(S, j, k, c);
       __syncthreads();
       gather_outputs<N, QUANT, false, BS>(S, sh, io);
     }
@@ -360,13 +367,13 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
       for (int v = 0; v < N; ++v) c[v] >>= 1;
     }
   }
-  write_column_rows<N, BS>(S, j, k, c);
+  if (j < KB) write_column_rows<N, BS>(S, j, k, c);
   __syncthreads();
 
-  // phase 3: rows, inverse
+  // phase 3: rows, inverse (columns >= KB are zero)
   const int i = a_idx;
   int z[N];
-  read_row<N, BS>(S, i, k, z);
+  read_row<N, BS, KB>(S, i, k, z);
   invN<KIND, N>(z);
   // zonal: Z = 4 X, y = round(Z / (4 N^2)); quantised: Z = 2 X~, y = round(X~ / (2 N^2))
   const unsigned long long e = store_row<N, DT, C::SROUND, NT>(

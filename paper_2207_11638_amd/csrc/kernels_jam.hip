@@ -67,8 +67,9 @@ __device__ __forceinline__ GroupIO plain_io(const PassParams& p, const WgPos& w)
 }
 
 // The workgroup walks p.gpw tile groups along its tile row and adds their
-// error energy to the image's total with one atomic.
-template <int KIND, int N, int DT, bool QUANT>
+// error energy to the image's total with one atomic.  KB: compile-time bound
+// on the kept rows and columns (zonal r <= KB (KB + 1) / 2), N otherwise.
+template <int KIND, int N, int DT, bool QUANT, int KB>
 __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
   using C = Cfg<N>;
   __shared__ int S[C::WORDS];
@@ -81,7 +82,8 @@ __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
   const int g1 = min(g0 + p.gpw, groups_x);
   unsigned long long e = 0;
   for (int gx = g0; gx < g1; ++gx)
-    e += compress_group<KIND, N, DT, QUANT>(S, sh, plain_io<N>(p, wg_pos_at<N>(p.g, gx, ty, img)));
+    e += compress_group<KIND, N, DT, QUANT, kBlock, true, KB>(
+        S, sh, plain_io<N>(p, wg_pos_at<N>(p.g, gx, ty, img)));
   if (p.sse != nullptr) block_add_sse<kBlock>(p.sse + img, e, red);
 }
 
@@ -196,8 +198,11 @@ hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
   const bool quant = p.qstep > 0;
   switch (mode) {
     case Mode::Compress:
-      if (quant) compress_jam<KIND, N, DT, true><<<grid, kBlock, 0, s>>>(p);
-      else compress_jam<KIND, N, DT, false><<<grid, kBlock, 0, s>>>(p);
+      // kept bound: r <= 10 keeps anti-diagonals 0..3, r <= 36 anti-diagonals 0..7
+      if (quant) compress_jam<KIND, N, DT, true, N><<<grid, kBlock, 0, s>>>(p);
+      else if (p.r <= 10) compress_jam<KIND, N, DT, false, 4><<<grid, kBlock, 0, s>>>(p);
+      else if (p.r <= 36) compress_jam<KIND, N, DT, false, 8><<<grid, kBlock, 0, s>>>(p);
+      else compress_jam<KIND, N, DT, false, N><<<grid, kBlock, 0, s>>>(p);
       break;
     case Mode::Forward:
       forward_jam<KIND, N, DT><<<grid, kBlock, 0, s>>>(p);
