@@ -121,8 +121,9 @@ __device__ __forceinline__ void item8(const Outs& o, const BItem& it, const TAB&
   if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
 }
 
-// One item of 16x16 / 32x32 TUs: BS / N tiles.
-template <int DT, int KIND, int N, bool QUANT, int BS, typename TAB>
+// One item of 16x16 / 32x32 TUs: BS / N tiles.  KB: compile-time kept bound
+// of the item's bucket (4, 8 or N).
+template <int DT, int KIND, int N, bool QUANT, int BS, int KB, typename TAB>
 __device__ __forceinline__ void item_jam(const Outs& o, const BItem& it, const TAB& t, int* S,
                                          jam::Shared<N>& sh, unsigned long long* red) {
   constexpr int esize = DT == DT_U8 ? 1 : 2;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void item_jam(const Outs& o, const BItem& it, const T
   io.kept = o.kept != nullptr ? o.kept + it.kept_base : nullptr;
   io.scaled = o.scaled != nullptr ? o.scaled + it.kept_base : nullptr;
   io.sse = o.sse != nullptr;
-  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false>(S, sh, io);
+  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false, KB>(S, sh, io);
   if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
 }
 
@@ -162,14 +163,14 @@ __global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
 }
 
 // 16x16 / 32x32 TUs: BS / N tiles per workgroup.
-template <int DT, int KIND, int N, bool QUANT, int BS>
+template <int DT, int KIND, int N, bool QUANT, int BS, int KB>
 __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
   using C = jam::Cfg<N, BS>;
   __shared__ int S[C::WORDS];
   __shared__ jam::Shared<N> sh;
   __shared__ unsigned long long red[BS / 64];
   const BItem it = p.items[p.item_begin + blockIdx.x];
-  item_jam<DT, KIND, N, QUANT, BS>(outs_of(p), it, p.t, S, sh, red);
+  item_jam<DT, KIND, N, QUANT, BS, KB>(outs_of(p), it, p.t, S, sh, red);
 }
 
 // ------------------------------------------------------------ unified launch
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
 // memory-side cache).  The workgroup branches (uniformly) to the code of its
 // bucket: the same device functions as the per-bucket kernels.
 struct UBucket {
-  int32_t code;       // 0..3: 8x8 staged T1, T2, unstaged T1, T2; 4, 5: 16x16 T1, T2; 6, 7: 32x32
+  int32_t code;       // 0..3: 8x8 staged T1, T2, unstaged T1, T2; 4..9: 16x16,
+                      // 10..15: 32x32, each as 4 + 6 [n = 32] + 2 [kept bound 4, 8, n] + T - 1
   int32_t pad[3];
   Tables t;
 };
@@ -216,6 +218,12 @@ __device__ __forceinline__ int xcd_slice_item(int b, int g) {
   return x * q + min(x, m) + j;
 }
 
+template <int N>
+__device__ __forceinline__ jam::Shared<N>& sh_of(jam::Shared<16>& a, jam::Shared<32>& b) {
+  if constexpr (N == 16) return a;
+  else return b;
+}
+
 template <int DT, bool QUANT>
 __global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
   __shared__ int S[kUnifiedWords];
@@ -230,10 +238,23 @@ __global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
     case 1: item8<DT, KIND_ROUND, QUANT, true, 256>(o, it, b.t, S, red); break;
     case 2: item8<DT, KIND_SIGN, QUANT, false, 256>(o, it, b.t, S, red); break;
     case 3: item8<DT, KIND_ROUND, QUANT, false, 256>(o, it, b.t, S, red); break;
-    case 4: item_jam<DT, KIND_SIGN, 16, QUANT, 256>(o, it, b.t, S, sh16, red); break;
-    case 5: item_jam<DT, KIND_ROUND, 16, QUANT, 256>(o, it, b.t, S, sh16, red); break;
-    case 6: item_jam<DT, KIND_SIGN, 32, QUANT, 256>(o, it, b.t, S, sh32, red); break;
-    default: item_jam<DT, KIND_ROUND, 32, QUANT, 256>(o, it, b.t, S, sh32, red); break;
+    // quantised buckets always use the full bound; their kept-bound cases are
+    // never reached and are not instantiated
+#define ADCT_UJZ(C, K, NN, KB) \
+    case C: if constexpr (!QUANT) item_jam<DT, K, NN, QUANT, 256, KB>(o, it, b.t, S, sh_of<NN>(sh16, sh32), red); break;
+    ADCT_UJZ(4, KIND_SIGN, 16, 4)
+    ADCT_UJZ(5, KIND_ROUND, 16, 4)
+    ADCT_UJZ(6, KIND_SIGN, 16, 8)
+    ADCT_UJZ(7, KIND_ROUND, 16, 8)
+    case 8: item_jam<DT, KIND_SIGN, 16, QUANT, 256, 16>(o, it, b.t, S, sh16, red); break;
+    case 9: item_jam<DT, KIND_ROUND, 16, QUANT, 256, 16>(o, it, b.t, S, sh16, red); break;
+    ADCT_UJZ(10, KIND_SIGN, 32, 4)
+    ADCT_UJZ(11, KIND_ROUND, 32, 4)
+    ADCT_UJZ(12, KIND_SIGN, 32, 8)
+    ADCT_UJZ(13, KIND_ROUND, 32, 8)
+    case 14: item_jam<DT, KIND_SIGN, 32, QUANT, 256, 32>(o, it, b.t, S, sh32, red); break;
+    default: item_jam<DT, KIND_ROUND, 32, QUANT, 256, 32>(o, it, b.t, S, sh32, red); break;
+#undef ADCT_UJZ
   }
 }
 
@@ -257,6 +278,7 @@ struct Bucket {
   int kind = 1;
   int qstep = 0;
   bool staged = true;    // 8x8 only
+  int kb = 0;            // 16x16 / 32x32: kept bound (4, 8 or n)
   int bs = 256;          // threads per workgroup
   Tables tables{};
   int64_t tu_begin = 0;  // first TU in the sorted order
@@ -284,15 +306,23 @@ void launch_bucket_typed(const Bucket& b, BucketParams p, int first, int count, 
       else { if (q) ADCT_B8(true, false, 256); else ADCT_B8(false, false, 256); }
     }
   } else {
-#define ADCT_BJ(NN, Q, BS) bucket_jam<DT, KIND, NN, Q, BS><<<grid, BS, 0, s>>>(p)
+#define ADCT_BJ(NN, Q, BS, KB) bucket_jam<DT, KIND, NN, Q, BS, KB><<<grid, BS, 0, s>>>(p)
+#define ADCT_BJS(NN, BS)                                          \
+    do {                                                          \
+      if (q) ADCT_BJ(NN, true, BS, NN);                           \
+      else if (b.kb == 4) ADCT_BJ(NN, false, BS, 4);              \
+      else if (b.kb == 8) ADCT_BJ(NN, false, BS, 8);              \
+      else ADCT_BJ(NN, false, BS, NN);                            \
+    } while (0)
     const bool q = b.qstep > 0;
     if (b.log2n == 4) {
-      if (b.bs == 128) { if (q) ADCT_BJ(16, true, 128); else ADCT_BJ(16, false, 128); }
-      else { if (q) ADCT_BJ(16, true, 256); else ADCT_BJ(16, false, 256); }
+      if (b.bs == 128) ADCT_BJS(16, 128);
+      else ADCT_BJS(16, 256);
     } else {
-      if (b.bs == 128) { if (q) ADCT_BJ(32, true, 128); else ADCT_BJ(32, false, 128); }
-      else { if (q) ADCT_BJ(32, true, 256); else ADCT_BJ(32, false, 256); }
+      if (b.bs == 128) ADCT_BJS(32, 128);
+      else ADCT_BJS(32, 256);
     }
+#undef ADCT_BJS
 #undef ADCT_BJ
   }
 #undef ADCT_B8
@@ -414,7 +444,9 @@ hipError_t build_unified(adct_batch* b, const std::vector<int2>& pos) {
   std::vector<UBucket> ub(b->buckets.size());
   for (size_t bi = 0; bi < b->buckets.size(); ++bi) {
     const Bucket& k = b->buckets[bi];
-    const int code = k.log2n == 3 ? (k.staged ? 0 : 2) : (k.log2n == 4 ? 4 : 6);
+    const int n = 8 << (k.log2n - 3);
+    const int kbi = k.kb == 4 ? 0 : (k.kb == 8 ? 1 : 2);
+    const int code = k.log2n == 3 ? (k.staged ? 0 : 2) : 4 + (n == 32 ? 6 : 0) + 2 * kbi;
     ub[bi].code = code + (k.kind == KIND_SIGN ? 0 : 1);
     ub[bi].pad[0] = ub[bi].pad[1] = ub[bi].pad[2] = 0;
     ub[bi].t = k.tables;
@@ -526,7 +558,7 @@ hipError_t enqueue_run(const adct_batch* b, const void* src, void* dst, int32_t*
 std::string tune_key(const adct_batch* b, const Bucket& k) {
   char buf[256];
   snprintf(buf, sizeof(buf), "%s:dt%d:n%d:k%d:q%d:st%d:tus%lld:img%d", b->arch.c_str(), b->dtype,
-           8 << (k.log2n - 3), k.kind, k.qstep, int(k.staged),
+           8 << (k.log2n - 3), k.kind, k.qstep, int(k.staged) + 2 * k.kb,
            (long long)(k.tu_end - k.tu_begin), static_cast<int>(k.image_ranges.size()));
   return buf;
 }
@@ -621,12 +653,16 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
   for (char& c : b->arch)
     if (c == ' ' || c == ':') c = '_';
 
-  // bucket key of a TU: (size, transform, step, staged)
+  // bucket key of a TU: (size, transform, step, staged, kept bound)
   auto key_of = [&](const adct_tu_desc_t& u) {
     const adct_image_desc_t& im = images[u.image];
     const int log2n = u.n == 8 ? 3 : (u.n == 16 ? 4 : 5);
     const bool staged = u.n != 8 || std::min(im.r, 64) <= kStagedRB;
-    return std::make_tuple(log2n, im.transform, im.qstep, staged);
+    // 16x16 / 32x32 zonal: every kept coefficient has v, u < 4 when r <= 10 and
+    // < 8 when r <= 36 (the zig-zag prefix of 4 or 8 anti-diagonals)
+    const int r = std::min(im.r, u.n * u.n);
+    const int kb = u.n == 8 ? 0 : (im.qstep > 0 ? u.n : (r <= 10 ? 4 : (r <= 36 ? 8 : u.n)));
+    return std::make_tuple(log2n, im.transform, im.qstep, staged, kb);
   };
   std::vector<int64_t> order(n_tus);
   for (int64_t t = 0; t < n_tus; ++t) order[t] = t;
@@ -654,6 +690,7 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
     k.kind = std::get<1>(key);
     k.qstep = std::get<2>(key);
     k.staged = std::get<3>(key);
+    k.kb = std::get<4>(key);
     k.bs = 256;
     if (int st = build_tables_for(k.kind, 8 << (k.log2n - 3), k.qstep, &k.tables)) {
       free_plan(b);
