@@ -204,6 +204,11 @@ typedef struct adct_batch adct_batch_t;
 #define ADCT_RUN_PER_IMAGE 2 /* one launch per image and bucket (baseline)       */
 #define ADCT_RUN_UNIFIED 3   /* one launch per quantiser class covering every     */
                              /* bucket, items of all sizes in image/position order */
+/* The zonal class of the unified launch runs every TU size one tile row per
+ * thread when none of its 16x16 / 32x32 TUs keeps more than r = 36 (the
+ * first 8 anti-diagonals): only 8 rows or columns of a tile then cross LDS,
+ * and the launch fits more workgroups per compute unit (adct_batch_info
+ * reports which form a plan uses). */
 
 /* Build a plan (host arrays in, device work list out; allocates device memory
  * and synchronises the device).  dtype is ADCT_U8 or ADCT_I16 for every
@@ -251,8 +256,10 @@ ADCT_API int adct_batch_set_shape(adct_batch_t* plan, int bs8, int bs_jam);
 ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
                              float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen);
 
-/* Work-list statistics (bookkeeping): out[0..7] = images, TUs, work items,
- * items of size 8, 16 and 32, buckets, compute units of the device. */
+/* Work-list statistics (bookkeeping): out[0..9] = images, TUs, work items,
+ * items of size 8, 16 and 32, buckets, compute units of the device, items
+ * of the unified launches, and 1 when the zonal unified launch is the
+ * row-per-thread form for kept bounds <= 8 (else 0). */
 ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
 
 /* ----------------------------------------------------------------------

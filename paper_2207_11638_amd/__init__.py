@@ -234,9 +234,10 @@ class BatchPlan:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         _lib.check(_lib.load().adct_batch_info(self._h, out.ctypes.data))
-        keys = ("images", "tus", "items", "items8", "items16", "items32", "buckets", "cus")
+        keys = ("images", "tus", "items", "items8", "items16", "items32", "buckets", "cus",
+                "unified_items", "small_bound")
         return dict(zip(keys, out.tolist()))
 
     def set_shape(self, bs8: int, bs_jam: int):

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(BS) void bucket8(BucketParams p) {
 // 16x16 / 32x32 TUs: BS / N tiles per workgroup.
 template <int DT, int KIND, int N, bool QUANT, int BS, int KB>
 __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
-  using C = jam::Cfg<N, BS>;
+  using C = jam::Cfg<N, BS, KB>;
   __shared__ int S[C::WORDS];
   __shared__ jam::Shared<N> sh;
   __shared__ unsigned long long red[BS / 64];
@@ -184,7 +184,9 @@ __global__ __launch_bounds__(BS) void bucket_jam(BucketParams p) {
 struct UBucket {
   int32_t code;       // 0..3: 8x8 staged T1, T2, unstaged T1, T2; 4..9: 16x16,
                       // 10..15: 32x32, each as 4 + 6 [n = 32] + 2 [kept bound 4, 8, n] + T - 1
-  int32_t pad[3];
+  int32_t small_code; // small-bound launch: 0, 1: 8x8 T1, T2; 2..5: 16x16, 6..9: 32x32,
+                      // each as 2 + 4 [n = 32] + 2 [kept bound 8] + T - 1
+  int32_t pad[2];
   Tables t;
 };
 
@@ -255,6 +257,94 @@ __global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
     case 14: item_jam<DT, KIND_SIGN, 32, QUANT, 256, 32>(o, it, b.t, S, sh32, red); break;
     default: item_jam<DT, KIND_ROUND, 32, QUANT, 256, 32>(o, it, b.t, S, sh32, red); break;
 #undef ADCT_UJZ
+  }
+}
+
+// ------------------------------------------------ unified launch, small bound
+// When no 16x16 or 32x32 bucket of the zonal class keeps more than the first
+// 8 anti-diagonals (r <= 36), every size runs as row groups (one tile row per
+// thread, the 8x8 TUs included) and at most 8 columns or rows of a tile cross
+// LDS.  The launch then needs far less LDS and fewer registers per workgroup
+// than the general one, which holds 64 pixels per thread for its 8x8 TUs and
+// a full 32x32 exchange buffer, so more workgroups share a compute unit to
+// hide the latency of the short items.  An item holds 8 groups of 32 8x8
+// TUs, 4 groups of 16 16x16 TUs (16 KB of pixels each) or one group of 8
+// 32x32 TUs (8 KB), processed one group after the other with the tables
+// loaded once and one error-energy atomic per item.  The 32x32 item stays a
+// single group: the group loop would keep enough state live to cost 30
+// registers, and the launch's occupancy is set by its largest path.
+constexpr int kSmallGroups[3] = {8, 4, 1};   // groups per item, n = 8, 16, 32
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kSmallWords =
+    cmax(jam::Cfg<8, 256, 8>::WORDS,
+         cmax(cmax(jam::Cfg<16, 256, 4>::WORDS, jam::Cfg<16, 256, 8>::WORDS),
+              cmax(jam::Cfg<32, 256, 4>::WORDS, jam::Cfg<32, 256, 8>::WORDS)));
+
+union SmallShared {
+  jam::Shared<8> n8;
+  jam::Shared<16> n16;
+  jam::Shared<32> n32;
+};
+
+// One item of row groups of N x N TUs with kept bound KB: its groups of
+// C::TPW TUs one after the other (GROUPS = 1: a single group, without the
+// loop, whose live state costs registers).
+template <int DT, int KIND, int N, int BS, int KB, int GROUPS, typename TAB>
+__device__ __forceinline__ void item_rows(const Outs& o, const BItem& it, const TAB& t, int* S,
+                                          jam::Shared<N>& sh, unsigned long long* red) {
+  constexpr int esize = DT == DT_U8 ? 1 : 2;
+  using C = jam::Cfg<N, BS, KB>;
+  const BImage im = o.imgs[it.image];
+  const int r = min(im.r, N * N);
+  jam::load_tables<N, BS>(sh, t, r);
+  const int k = threadIdx.x % C::TPW;
+  jam::GroupIO io;
+  io.src = offset_px(o.src, im.src_off, esize);
+  io.dst = offset_px(o.dst, im.dst_off, esize);
+  io.pitch = im.pitch;
+  io.r = r;
+  io.sse = o.sse != nullptr;
+  auto group = [&](int g) {
+    io.nact = min(C::TPW, it.count - g);
+    io.active = k < io.nact;
+    int2 xy = make_int2(0, 0);
+    if (io.active) xy = o.pos[it.tu_begin + g + k];
+    io.tile_pix = static_cast<int64_t>(xy.y) * im.pitch + xy.x;
+    const int64_t kb = it.kept_base + static_cast<int64_t>(g) * r;
+    io.kept = o.kept != nullptr ? o.kept + kb : nullptr;
+    io.scaled = o.scaled != nullptr ? o.scaled + kb : nullptr;
+    return jam::compress_group<KIND, N, DT, false, BS, false, KB>(S, sh, io);
+  };
+  unsigned long long e = 0;
+  if constexpr (GROUPS == 1) {
+    e = group(0);
+  } else {
+    for (int g = 0; g < it.count; g += C::TPW) e += group(g);
+  }
+  if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void bucket_unified_small(UnifiedParams p) {
+  __shared__ int S[kSmallWords];
+  __shared__ SmallShared sh;
+  __shared__ unsigned long long red[4];
+  const BItem it = p.items[xcd_slice_item(blockIdx.x, gridDim.x)];
+  const UBucket& b = p.buckets[it.pad];
+  const Outs o{p.imgs, p.pos, p.src, p.dst, p.kept, p.scaled, p.sse};
+  constexpr int G8 = kSmallGroups[0], G16 = kSmallGroups[1], G32 = kSmallGroups[2];
+  switch (b.small_code) {
+    case 0: item_rows<DT, KIND_SIGN, 8, 256, 8, G8>(o, it, b.t, S, sh.n8, red); break;
+    case 1: item_rows<DT, KIND_ROUND, 8, 256, 8, G8>(o, it, b.t, S, sh.n8, red); break;
+    case 2: item_rows<DT, KIND_SIGN, 16, 256, 4, G16>(o, it, b.t, S, sh.n16, red); break;
+    case 3: item_rows<DT, KIND_ROUND, 16, 256, 4, G16>(o, it, b.t, S, sh.n16, red); break;
+    case 4: item_rows<DT, KIND_SIGN, 16, 256, 8, G16>(o, it, b.t, S, sh.n16, red); break;
+    case 5: item_rows<DT, KIND_ROUND, 16, 256, 8, G16>(o, it, b.t, S, sh.n16, red); break;
+    case 6: item_rows<DT, KIND_SIGN, 32, 256, 4, G32>(o, it, b.t, S, sh.n32, red); break;
+    case 7: item_rows<DT, KIND_ROUND, 32, 256, 4, G32>(o, it, b.t, S, sh.n32, red); break;
+    case 8: item_rows<DT, KIND_SIGN, 32, 256, 8, G32>(o, it, b.t, S, sh.n32, red); break;
+    default: item_rows<DT, KIND_ROUND, 32, 256, 8, G32>(o, it, b.t, S, sh.n32, red); break;
   }
 }
 
@@ -359,6 +449,7 @@ struct adct_batch {
   // unified launches: one item list per quantiser class (zonal, quantised)
   struct Unified {
     bool quant = false;
+    bool small = false;             // zonal, no 16x16 / 32x32 bucket with kept bound > 8
     std::vector<BItem> items;
     BItem* d_items = nullptr;
   };
@@ -442,13 +533,20 @@ hipError_t build_items(adct_batch* b, Bucket& k) {
 // device table of bucket codes and constant tables.
 hipError_t build_unified(adct_batch* b, const std::vector<int2>& pos) {
   std::vector<UBucket> ub(b->buckets.size());
+  // the zonal class runs as the small-bound launch when none of its 16x16 /
+  // 32x32 buckets has a kept bound above 8
+  bool small = true;
+  for (const Bucket& k : b->buckets)
+    if (k.qstep == 0 && k.log2n > 3 && k.kb > 8) small = false;
   for (size_t bi = 0; bi < b->buckets.size(); ++bi) {
     const Bucket& k = b->buckets[bi];
     const int n = 8 << (k.log2n - 3);
     const int kbi = k.kb == 4 ? 0 : (k.kb == 8 ? 1 : 2);
     const int code = k.log2n == 3 ? (k.staged ? 0 : 2) : 4 + (n == 32 ? 6 : 0) + 2 * kbi;
-    ub[bi].code = code + (k.kind == KIND_SIGN ? 0 : 1);
-    ub[bi].pad[0] = ub[bi].pad[1] = ub[bi].pad[2] = 0;
+    const int t2 = k.kind == KIND_SIGN ? 0 : 1;
+    ub[bi].code = code + t2;
+    ub[bi].small_code = k.log2n == 3 ? t2 : 2 + (n == 32 ? 4 : 0) + 2 * (k.kb == 8) + t2;
+    ub[bi].pad[0] = ub[bi].pad[1] = 0;
     ub[bi].t = k.tables;
     const int quant = k.qstep > 0 ? 1 : 0;
     size_t u = 0;
@@ -456,8 +554,10 @@ hipError_t build_unified(adct_batch* b, const std::vector<int2>& pos) {
     if (u == b->unified.size()) {
       b->unified.emplace_back();
       b->unified.back().quant = quant;
+      b->unified.back().small = !quant && small;
     }
-    const int cap = k.log2n == 3 ? 256 : 256 >> k.log2n;
+    const int cap = b->unified[u].small ? (256 >> k.log2n) * kSmallGroups[k.log2n - 3]
+                                        : (k.log2n == 3 ? 256 : 256 >> k.log2n);
     int64_t t = k.tu_begin;
     while (t < k.tu_end) {
       const int img = b->tu_image[t];
@@ -500,6 +600,11 @@ void launch_unified(const adct_batch* b, const adct_batch::Unified& u, const Uni
                     hipStream_t s) {
   if (u.items.empty()) return;
   const dim3 grid(static_cast<unsigned>(u.items.size()));
+  if (u.small) {
+    if (b->dtype == ADCT_U8) bucket_unified_small<DT_U8><<<grid, 256, 0, s>>>(p);
+    else bucket_unified_small<DT_I16><<<grid, 256, 0, s>>>(p);
+    return;
+  }
   if (b->dtype == ADCT_U8) {
     if (u.quant) bucket_unified<DT_U8, true><<<grid, 256, 0, s>>>(p);
     else bucket_unified<DT_U8, false><<<grid, 256, 0, s>>>(p);
@@ -762,6 +867,13 @@ ADCT_API int adct_batch_info(const adct_batch_t* b, int64_t* out) {
   out[5] = by[2];
   out[6] = static_cast<int64_t>(b->buckets.size());
   out[7] = b->cus;
+  int64_t unified_items = 0, small = 0;
+  for (const auto& u : b->unified) {
+    unified_items += static_cast<int64_t>(u.items.size());
+    if (u.small) small = 1;
+  }
+  out[8] = unified_items;
+  out[9] = small;
   return set_error(ADCT_OK, "");
 }
 

@@ -1,6 +1,7 @@
 // Workgroup-level processing of 16 x 16 and 32 x 32 tiles (Chen-JAM
 // transforms of section 6.1), shared by the plain kernels and the ragged
-// batch kernel.
+// batch kernel; the same code also runs 8 x 8 tiles (eqs. 4, 5 and 6, 7) in
+// the ragged batch, one thread per tile row.
 //
 // A workgroup of 256 threads owns TPW = 256/N tiles k = 0..TPW-1, each at its
 // own pixel offset.  Thread L plays two roles:
@@ -10,8 +11,13 @@
 // wave cover whole tile rows, so every pixel load/store of a wave is a run of
 // 256 B (uint8) or 512 B (int16) per image row.  Each 1D N-point butterfly
 // runs on N values in one thread's registers; the row<->column exchange goes
-// through LDS with a padded layout (column stride N+1, tile stride 2 or 4 mod
-// 32 words) that keeps every LDS access of a half-wave on distinct banks.
+// through LDS with a padded layout (column stride N+1, tile stride 32/TPW mod
+// 32 words) that keeps the LDS accesses of a half-wave on few banks.
+//
+// The kept bound KB (every retained coefficient has v, u < KB) also bounds
+// what crosses LDS: KB transformed columns after the row pass, KB coefficient
+// rows after the column pass and KB inverse columns before the last pass.
+// A tile then needs max(KB (N+1), N (KB+1)) words instead of N (N+1).
 #pragma once
 
 #include "adct_internal.hpp"
@@ -19,23 +25,31 @@
 namespace adct {
 namespace jam {
 
-// Smallest tile stride >= n * (n + 1) words that is congruent to `spread`
-// modulo 32: the TPW tiles of a half-wave then start on banks `spread` apart.
-constexpr int tile_stride(int n, int spread) {
-  int ts = n * (n + 1);
+// Smallest tile stride >= `words` that is congruent to `spread` modulo 32:
+// the TPW tiles of a half-wave then start on banks `spread` apart.
+constexpr int tile_stride(int words, int spread) {
+  int ts = words;
   while (ts % 32 != spread) ++ts;
   return ts;
 }
 
-template <int N, int BS = 256>
+// With 32 tiles per workgroup (N = 8) any odd stride puts the 32 tiles of a
+// half-wave on 32 distinct banks.
+constexpr int odd_stride(int words) { return words | 1; }
+
+template <int N, int BS = 256, int KB = N>
 struct Cfg {
   static constexpr int TPW = BS / N;                        // tiles per workgroup
-  static constexpr int CS = N + 1;                          // LDS column stride (words)
-  static constexpr int TS = tile_stride(N, 32 / TPW);       // LDS tile stride (words)
+  static constexpr int CS = N + 1;                          // column / coefficient-row stride
+  static constexpr int IS = KB + 1;                         // row stride of the inverse exchange
+  static constexpr int NEED = KB * CS > N * IS ? KB * CS : N * IS;
+  static constexpr int TS = TPW == 32 ? odd_stride(NEED)   // LDS tile stride (words)
+                                       : tile_stride(NEED, 32 / TPW);
   static constexpr int WORDS = TPW * TS;
-  static constexpr int LOG2N = N == 16 ? 4 : 5;
+  static constexpr int LOG2N = N == 8 ? 3 : (N == 16 ? 4 : 5);
   static constexpr int SROUND = 2 + 2 * LOG2N;              // divide by 4 N^2
   static_assert(TPW >= 2 && TPW <= 32, "unsupported block size");
+  static_assert(KB == 4 || KB == 8 || KB == N, "unsupported kept bound");
 };
 
 constexpr int kBlock = 256;
@@ -109,6 +123,14 @@ __device__ __forceinline__ void load_row(const void* src, int64_t off, bool acti
                                          RowWords<N, DT>& rw) {
   constexpr int V = RowWords<N, DT>::W / 4;  // uint4 per row
   const uint32_t fill = DT == DT_U8 ? 0x80808080u : 0u;
+  if constexpr (RowWords<N, DT>::W == 2) {   // 8 uint8 pixels
+    uint2 w = make_uint2(fill, fill);
+    if (active)
+      w = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(src) + off);
+    rw.w[0] = w.x;
+    rw.w[1] = w.y;
+    return;
+  }
   const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(src) +
                                                   off * (DT == DT_U8 ? 1 : 2));
 #pragma unroll
@@ -185,6 +207,11 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
     }
   }
   if (dst != nullptr && active) {
+    if constexpr (RowWords<N, DT>::W == 2) {   // 8 uint8 pixels
+      st_pix<NT>(reinterpret_cast<uint2*>(static_cast<uint8_t*>(dst) + off),
+                 make_uint2(yw.w[0], yw.w[1]));
+      return err;
+    }
     uint4* p = reinterpret_cast<uint4*>(static_cast<uint8_t*>(dst) + off * (DT == DT_U8 ? 1 : 2));
 #pragma unroll
     for (int q = 0; q < RowWords<N, DT>::W / 4; ++q)
@@ -200,26 +227,39 @@ __device__ __forceinline__ int quantise(int b, int32_t mq) {
   return b < 0 ? -lev : lev;
 }
 
-template <int N, int BS>
+// Column j of tile k after the row pass (stored column-major, j < KB).
+template <int N, int BS, int KB = N>
 __device__ __forceinline__ void read_column(const int* S, int j, int k, int (&c)[N]) {
-  using C = Cfg<N, BS>;
+  using C = Cfg<N, BS, KB>;
 #pragma unroll
   for (int v = 0; v < N; ++v) c[v] = S[k * C::TS + j * C::CS + v];
 }
 
-template <int N, int BS, int ROWS = N>
+// Rows v < ROWS of column j into the coefficient layout [k][v][u] (row stride
+// N + 1, the layout the zig-zag table addresses).
+template <int N, int BS, int ROWS = N, int KB = N>
 __device__ __forceinline__ void write_column_rows(int* S, int j, int k, const int (&c)[N]) {
-  using C = Cfg<N, BS>;
+  using C = Cfg<N, BS, KB>;
 #pragma unroll
   for (int v = 0; v < ROWS; ++v) S[k * C::TS + v * C::CS + j] = c[v];
 }
 
-// Row i of tile k; entries u >= COLS are zero and not read.
-template <int N, int BS, int COLS = N>
-__device__ __forceinline__ void read_row(const int* S, int i, int k, int (&z)[N]) {
-  using C = Cfg<N, BS>;
+// Inverse exchange: column j < KB of tile k after the inverse column pass,
+// stored row-major with row stride KB + 1.
+template <int N, int BS, int KB = N>
+__device__ __forceinline__ void write_inverse_column(int* S, int j, int k, const int (&c)[N]) {
+  using C = Cfg<N, BS, KB>;
 #pragma unroll
-  for (int u = 0; u < N; ++u) z[u] = u < COLS ? S[k * C::TS + i * C::CS + u] : 0;
+  for (int v = 0; v < N; ++v) S[k * C::TS + v * C::IS + j] = c[v];
+}
+
+// Row i of tile k from the inverse exchange; entries u >= KB are zero and
+// not read.
+template <int N, int BS, int KB = N>
+__device__ __forceinline__ void read_row(const int* S, int i, int k, int (&z)[N]) {
+  using C = Cfg<N, BS, KB>;
+#pragma unroll
+  for (int u = 0; u < N; ++u) z[u] = u < KB ? S[k * C::TS + i * C::IS + u] : 0;
 }
 
 // Copy ``count`` contiguous words from LDS to global memory (all threads).
@@ -235,10 +275,10 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
 // 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
 // LEVELS: S holds the quantisation levels already (no scaled output), so the
 // kept words are copied as they are.
-template <int N, bool QUANT, bool LEVELS, int BS>
+template <int N, bool QUANT, bool LEVELS, int BS, int KB = N>
 __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh,
                                                const GroupIO& io) {
-  using C = Cfg<N, BS>;
+  using C = Cfg<N, BS, KB>;
   const int r = io.r;
   const int total = io.nact * r;
   if (threadIdx.x >= total) return;
@@ -272,7 +312,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
 template <int KIND, int N, int DT, int BS, int KB = N>
 __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, int k,
                                             RowWords<N, DT>& x) {
-  using C = Cfg<N, BS>;
+  using C = Cfg<N, BS, KB>;
   load_row<N, DT>(io.src, io.tile_pix + static_cast<int64_t>(i) * io.pitch, io.active, x);
   int a[N];
   unpack_row<N, DT>(x, a);
@@ -294,7 +334,8 @@ __device__ __forceinline__ void row_forward(int* S, const GroupIO& io, int i, in
 // compiler removes the additions that only feed or read those.
 template <int KIND, int N, int DT, bool QUANT, int BS = kBlock, bool NT = true, int KB = N>
 __device__ __forceinline__ unsigned long long compress_group(int* S, const Shared<N>& sh, const GroupIO& io) {
-  using C = Cfg<N, BS>;
+  using C = Cfg<N, BS, KB>;
+  static_assert(!(QUANT && (N == 8 || KB != N)), "quantised groups: N = 16, 32 with the full bound");
   constexpr RowClasses<N> RC = row_classes<KIND, N>();
   const int a_idx = threadIdx.x / C::TPW;
   const int k = threadIdx.x % C::TPW;
@@ -309,10 +350,10 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   // inverted: its transform is skipped, which whole waves do at small r
   // (a wave holds 64 / TPW consecutive columns).
   const int j = a_idx;
-  const int keep = sh.cnt[j];
+  const int keep = j < KB ? sh.cnt[j] : 0;
   int c[N];
   if (keep > 0) {
-    read_column<N, BS>(S, j, k, c);
+    read_column<N, BS, KB>(S, j, k, c);
     fwdN<KIND, N>(c);
     if constexpr (DT == DT_U8)
       if (j == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
@@ -342,13 +383,13 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   }
   if (io.kept != nullptr || io.scaled != nullptr) {
     if (QUANT && io.scaled == nullptr) {
-      write_column_rows<N, BS, KB>(S, j, k, lev);   // [k][v][u], rows v < KB
+      write_column_rows<N, BS, KB, KB>(S, j, k, lev);   // [k][v][u], rows v < KB
       __syncthreads();
-      gather_outputs<N, QUANT, true, BS>(S, sh, io);
+      gather_outputs<N, QUANT, true, BS, KB>(S, sh, io);
     } else {
-      write_column_rows<N, BS, KB>(S, j, k, c);
+      write_column_rows<N, BS, KB, KB>(S, j, k, c);
       __syncthreads();
-      gather_outputs<N, QUANT, false, BS>(S, sh, io);
+      gather_outputs<N, QUANT, false, BS, KB>(S, sh, io);
     }
     __syncthreads();
   }
@@ -367,7 +408,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
       for (int v = 0; v < N; ++v) c[v] >>= 1;
     }
   }
-  if (j < KB) write_column_rows<N, BS>(S, j, k, c);
+  if (j < KB) write_inverse_column<N, BS, KB>(S, j, k, c);
   __syncthreads();
 
   // phase 3: rows, inverse (columns >= KB are zero)

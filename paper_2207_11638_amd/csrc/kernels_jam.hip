@@ -71,7 +71,7 @@ __device__ __forceinline__ GroupIO plain_io(const PassParams& p, const WgPos& w)
 // on the kept rows and columns (zonal r <= KB (KB + 1) / 2), N otherwise.
 template <int KIND, int N, int DT, bool QUANT, int KB>
 __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
-  using C = Cfg<N>;
+  using C = Cfg<N, kBlock, KB>;
   __shared__ int S[C::WORDS];
   __shared__ Shared<N> sh;
   __shared__ unsigned long long red[kBlock / 64];

@@ -21,7 +21,7 @@ from paper_2207_11638_amd import ragged  # noqa: E402
 DEV = torch.device("cuda:0")
 
 
-def make_set(kind, seed, n_images=7):
+def make_set(kind, seed, n_images=7, r_set=(1, 6, 10, 28, 45, 64, 1024)):
     rng = synth.rng_for(seed)
     sizes = [(64, 96), (40, 72), (96, 64), (8, 8), (136, 200), (32, 40), (72, 104)][:n_images]
     imgs, tus, kinds, rs, qs = [], [], [], [], []
@@ -32,7 +32,7 @@ def make_set(kind, seed, n_images=7):
             imgs.append(synth.laplace_residual(h, w, seed=seed + i))
         tus.append(synth.quadtree_tus(h, w, rng, p_split=0.4))
         kinds.append(1 + i % 2)
-        rs.append([1, 6, 10, 28, 45, 64, 1024][i % 7])
+        rs.append(r_set[i % len(r_set)])
         qs.append(0 if kind == "u8" or i % 3 == 0 else [8, 16, 64][i % 3])
     arena, descs = ragged.pack_images(imgs, kinds, rs, qs)
     return imgs, descs, ragged.tu_table(tus), arena
@@ -69,13 +69,19 @@ def run_plan(plan, arena, mode, stream=None):
             sse.cpu().numpy().astype(np.int64), psnr.cpu().numpy())
 
 
+# r_set: the default mixes kept bounds above 8 into the zonal class, so its
+# unified launch is the general one; the second keeps every r <= 36 and
+# selects the row-per-thread launch of small kept bounds
+@pytest.mark.parametrize("r_set,small", [((1, 6, 10, 28, 45, 64, 1024), 0),
+                                         ((1, 6, 10, 15, 21, 28, 36), 1)])
 @pytest.mark.parametrize("mode", ["batched", "unified"])
 @pytest.mark.parametrize("kind", ["u8", "i16"])
-def test_batch_matches_oracle_per_tu(kind, mode):
-    imgs, descs, tus, arena = make_set(kind, 5000 if kind == "u8" else 6000)
+def test_batch_matches_oracle_per_tu(kind, mode, r_set, small):
+    imgs, descs, tus, arena = make_set(kind, 5000 if kind == "u8" else 6000, r_set=r_set)
     plan = adct.BatchPlan(descs, tus, torch.uint8 if kind == "u8" else torch.int16)
     info = plan.info()
     assert info["tus"] == len(tus) and info["items8"] > 0 and info["items16"] > 0
+    assert info["small_bound"] == small and info["unified_items"] > 0
     dst, kept, scaled, sse, psnr = run_plan(plan, arena, mode)
     want_kept, want_scaled, want_recon, want_sse = oracle_expect(imgs, descs, tus)
     for t in range(len(tus)):
