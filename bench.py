@@ -752,8 +752,9 @@ def run_c3(args):
                                  "per_image_gpixel_s": round(npx / ms_per_image / 1e6, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "bucket_unified (graph replay of one launch over all buckets, "
-                               "XCD-sliced item order)"},
+                     "kernel": ("bucket_unified_small" if info.get("small_bound") else
+                                "bucket_unified") + " (graph replay of one launch over all "
+                               "buckets, XCD-sliced item order)"},
         "plan": info,
         "tuned_block_sizes": chosen.tolist(),
         "parity_sample": check,

@@ -111,10 +111,11 @@ __global__ __launch_bounds__(t8::kWave) void serve8(const SReq* reqs, const int*
   block_add_sse<t8::kWave>(rq.sse, e, nullptr);
 }
 
-template <int KIND, int N, int DT, bool QUANT>
+// KB: compile-time kept bound of the class (4, 8 or N; zonal r <= KB (KB + 1) / 2).
+template <int KIND, int N, int DT, bool QUANT, int KB>
 __global__ __launch_bounds__(jam::kBlock) void serve_jam(const SReq* reqs, const int* begins,
                                                          int n_req) {
-  using C = jam::Cfg<N>;
+  using C = jam::Cfg<N, jam::kBlock, KB>;
   __shared__ int S[C::WORDS];
   __shared__ jam::Shared<N> sh;
   __shared__ unsigned long long red[jam::kBlock / 64];
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(jam::kBlock) void serve_jam(const SReq* reqs, const
   io.scaled = rq.scaled != nullptr ? rq.scaled + tile0 * rq.r : nullptr;
   io.sse = true;
   const unsigned long long e =
-      jam::compress_group<KIND, N, DT, QUANT, jam::kBlock, false>(S, sh, io);
+      jam::compress_group<KIND, N, DT, QUANT, jam::kBlock, false, KB>(S, sh, io);
   block_add_sse<jam::kBlock>(rq.sse, e, red);
 }
 
@@ -158,10 +159,13 @@ struct ClassKey {
   bool operator!=(const ClassKey& o) const { return o < *this || *this < o; }
 };
 
-// Compile-time bound on r of the 8x8 kernel used for a request: the
-// arithmetic that only feeds zig-zag positions >= RB is dropped.
+// Compile-time bound of the kernel used for a request.  8x8: a bound on r
+// (the arithmetic that only feeds zig-zag positions >= RB is dropped).
+// 16x16 / 32x32: the kept bound KB, every kept coefficient having v, u < KB
+// (4 for zonal r <= 10, 8 for r <= 36: the zig-zag prefixes of 4 and 8
+// anti-diagonals), which prunes the butterflies and the LDS exchanges.
 int rb_of(int n, int r, int qstep) {
-  if (n != 8) return 0;
+  if (n != 8) return qstep > 0 ? n : (r <= 10 ? 4 : (r <= 36 ? 8 : n));
   if (qstep > 0) return 64;
   return r <= 10 ? 10 : (r <= 28 ? 28 : 64);
 }
@@ -378,11 +382,15 @@ void launch_class_typed(const ClassKey& c, dim3 grid, hipStream_t st, const SReq
     else if (c.rb == 28) serve8<KIND, DT, 28, false><<<grid, t8::kWave, 0, st>>>(r, b, nq);
     else serve8<KIND, DT, 64, false><<<grid, t8::kWave, 0, st>>>(r, b, nq);
   } else if (c.n == 16) {
-    if (c.quant) serve_jam<KIND, 16, DT, true><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
-    else serve_jam<KIND, 16, DT, false><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    if (c.quant) serve_jam<KIND, 16, DT, true, 16><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else if (c.rb == 4) serve_jam<KIND, 16, DT, false, 4><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else if (c.rb == 8) serve_jam<KIND, 16, DT, false, 8><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else serve_jam<KIND, 16, DT, false, 16><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
   } else {
-    if (c.quant) serve_jam<KIND, 32, DT, true><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
-    else serve_jam<KIND, 32, DT, false><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    if (c.quant) serve_jam<KIND, 32, DT, true, 32><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else if (c.rb == 4) serve_jam<KIND, 32, DT, false, 4><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else if (c.rb == 8) serve_jam<KIND, 32, DT, false, 8><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
+    else serve_jam<KIND, 32, DT, false, 32><<<grid, jam::kBlock, 0, st>>>(r, b, nq);
   }
 }
 
