@@ -21,7 +21,9 @@
  *   dtype      ADCT_U8: 8-bit grey levels, shifted by -128 before the
  *              transform and reconstructed as round(.) + 128 clipped to
  *              [0, 255].  ADCT_I16: signed 16-bit prediction residuals, not
- *              shifted, reconstruction saturated to int16.
+ *              shifted, reconstruction saturated to int16.  Every int16
+ *              value is accepted: the int32 intermediates of all n, r and
+ *              qstep stay exact over the whole int16 range.
  *   image set  ``batch`` images of ``height`` x ``width`` pixels (both
  *              multiples of n).  Row y of image i starts at element
  *              i * image_stride + y * pitch (strides in pixels, not bytes).

@@ -134,6 +134,50 @@ def test_extreme_images(kind, n):
     compare_compress(res, kind, n, n * n, 4096)
 
 
+def worst_case_tiles(kind, n, r, count=8):
+    """Full-range int16 tiles that maximise |X[i][j]| of the exact inverse
+    X = U mask_r(T A T^T) U^T (eqs. 6/7 and section 6.1 with U = N T^-1, the
+    zig-zag mask of section 5.1): X[i][j] is the linear form
+    sum_ab C_ij[a][b] A[a][b], largest at A = 32767 sign(C_ij) (-32768 where
+    the sign is negative).  One tile for each of the `count` largest forms."""
+    T = M.transform_matrix(kind, n).astype(np.float64)
+    U = M.scaled_inverse(kind, n).astype(np.float64)
+    m = np.zeros((n, n))
+    for p in M.zigzag(n)[:r]:
+        m[p] = 1.0
+    G = np.einsum("iv,vu,va->iua", U, m, T)          # (i, u, a)
+    H = np.einsum("ju,ub->jub", U, T)                # (j, u, b)
+    C = (G.transpose(0, 2, 1).reshape(n * n, n) @ H.transpose(1, 0, 2).reshape(n, n * n))
+    C = C.reshape(n, n, n, n).transpose(0, 2, 1, 3)  # (i, j, a, b)
+    l1 = np.abs(C).sum(axis=(2, 3)).reshape(-1)
+    tiles = []
+    for k in np.argsort(l1)[::-1][:count]:
+        s = np.sign(C[k // n, k % n])
+        tiles.append(np.where(s > 0, 32767, np.where(s < 0, -32768, 0)).astype(np.int16))
+    return tiles
+
+
+# retention levels over the whole range, including the ones where the largest
+# intermediate of the 16- and 32-point inverses peaks
+WORST_R = {8: (4, 11, 31, 47, 64), 16: (37, 56, 146, 173, 256),
+           32: (172, 407, 692, 768, 1024)}
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_full_range_int16_worst_case(kind, n):
+    # int16 inputs are exact over their whole range: every intermediate of
+    # the fused path stays within int32 for any r and any step up to 4096
+    for r in WORST_R[n]:
+        tiles = worst_case_tiles(kind, n, r)
+        row = np.concatenate(tiles, axis=1)
+        img = np.concatenate([row, (-row.astype(np.int32)).clip(-32768, 32767).astype(np.int16)])
+        compare_compress([img], kind, n, r)
+        if r == n * n:
+            for q in (1, 16, 4096):
+                compare_compress([img], kind, n, r, q)
+
+
 @pytest.mark.parametrize("n", [8, 16, 32])
 def test_strided_geometry(n):
     # pitch > width and image stride > pitch * height, through tensor views

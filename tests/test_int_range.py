@@ -1,0 +1,171 @@
+"""Integer range of the fused path: every intermediate fits int32 for every
+input the API accepts (uint8, and int16 over its whole range).
+
+Each node of the kernels' butterflies is a linear form of the tile's pixels,
+so over |x| <= M its largest magnitude is M times the L1 norm of the form.
+The model below runs the node structure of the 8-point factorisation (eqs.
+4-7: B8, M4, M3, M2, M1 and P8 forward; their inverses with K8 = 16 T^-1)
+and of the Chen-JAM recursion (section 6.1, K_N = 2N T_N^-1) on linear
+forms instead of numbers.  The model is first checked against the oracle's
+T_N and N T_N^-1, then used to bound every node of the 2D path:
+  forward rows, forward columns, inverse columns (zig-zag mask applied or
+  dequantised levels), inverse rows."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import matrices as M
+
+INT32 = 2 ** 31 - 1
+XMAX = 32768                      # largest |int16|
+
+
+class Forms:
+    """Collects the L1 norm of every node created while a butterfly runs."""
+
+    def __init__(self):
+        self.peak = 0.0
+
+    def __call__(self, v):
+        a = np.abs(v)
+        norm = a.reshape(a.shape[0], -1).sum(1).max() if a.ndim > 1 else a.sum()
+        self.peak = max(self.peak, float(norm))
+        return v
+
+
+def fwd8(x, kind, t):
+    y = [t(x[0] + x[7]), t(x[1] + x[6]), t(x[2] + x[5]), t(x[3] + x[4]),
+         t(x[3] - x[4]), t(x[2] - x[5]), t(x[1] - x[6]), t(x[0] - x[7])]
+    z0, z1, z2, z3 = t(y[0] + y[3]), t(y[1] + y[2]), t(y[1] - y[2]), t(y[0] - y[3])
+    z4, z5, z6, z7 = y[7], t(y[5] + y[6]), t(y[6] - y[5]), y[4]
+    w0, w1 = t(z0 + z1), t(z0 - z1)
+    w2, w3 = (t(z3 - z2), t(z2 + z3)) if kind == M.SIGN else (-z2, z3)
+    w4, w5, w6, w7 = t(z4 + z5), t(z4 - z5), t(z7 - z6), t(z6 + z7)
+    v4, v7 = (t(w4 + w7), t(w4 - w7)) if kind == M.SIGN else (w4, -w7)
+    v5, v6 = t(w5 + w6), t(w5 - w6)
+    return [w0, v4, w3, v6, w1, v5, w2, v7]
+
+
+def inv8(X, kind, t):
+    v0, v1, v2, v3, v4, v5, v6, v7 = X[0], X[2], X[4], X[6], X[1], X[5], X[3], X[7]
+    w0, w1, w2, w3 = t(2 * v0), t(2 * v2), t(2 * v3), t(2 * v1)
+    w4, w7 = (t(v4 + v7), t(v4 - v7)) if kind == M.SIGN else (t(2 * v4), t(-2 * v7))
+    w5, w6 = t(v5 + v6), t(v5 - v6)
+    z0, z1 = t(w0 + w1), t(w0 - w1)
+    z2, z3 = (t(w3 - w2), t(w2 + w3)) if kind == M.SIGN else (t(-2 * w2), t(2 * w3))
+    z4, z5, z6, z7 = t(w4 + w5), t(w4 - w5), t(w7 - w6), t(w6 + w7)
+    y0, y1, y2, y3 = t(z0 + z3), t(z1 + z2), t(z1 - z2), t(z0 - z3)
+    y4, y5, y6, y7 = t(2 * z7), t(z5 - z6), t(z5 + z6), t(2 * z4)
+    return [t(y0 + y7), t(y1 + y6), t(y2 + y5), t(y3 + y4),
+            t(y3 - y4), t(y2 - y5), t(y1 - y6), t(y0 - y7)]
+
+
+def fwd(x, kind, t):
+    n = len(x)
+    if n == 8:
+        return fwd8(x, kind, t)
+    h = n // 2
+    u = fwd([t(x[i] + x[n - 1 - i]) for i in range(h)], kind, t)
+    w = fwd([t(x[h - 1 - i] - x[h + i]) for i in range(h)], kind, t)
+    return [u[k // 2] if k % 2 == 0 else w[k // 2] for k in range(n)]
+
+
+def inv(X, kind, t):
+    n = len(X)
+    if n == 8:
+        return inv8(X, kind, t)
+    h = n // 2
+    p = inv([X[2 * k] for k in range(h)], kind, t)
+    q = inv([X[2 * k + 1] for k in range(h)], kind, t)
+    return [t(p[i] + q[h - 1 - i]) for i in range(h)] + [t(p[h - 1 - i] - q[i]) for i in range(h)]
+
+
+def unit(n):
+    return [np.eye(n)[i] for i in range(n)]
+
+
+def peak(fn, forms, kind):
+    t = Forms()
+    fn(forms, kind, t)
+    return t.peak
+
+
+def mask(n, r):
+    m = np.zeros((n, n))
+    for p in M.zigzag(n)[:r]:
+        m[p] = 1.0
+    return m
+
+
+def inverse_peaks(kind, n, w):
+    """Largest node norms of the inverse column and row passes when the
+    inverse sees w[v][u] * b[v][u] (w: mask or per-coefficient weights)."""
+    T = M.transform_matrix(kind, n).astype(np.float64)
+    K = 2 * M.scaled_inverse(kind, n).astype(np.float64)
+    t1 = np.abs(T).sum(1)
+    cols = max(peak(inv, [w[v, u] * T[v] for v in range(n)], kind) * t1[u]
+               for u in range(n) if w[:, u].any())
+    g = np.einsum("iv,vu,va->iua", K, w, T)
+    rows = peak(inv, [np.einsum("ia,b->iab", g[:, u, :], T[u]) for u in range(n)], kind)
+    return cols, rows
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_model_computes_the_transform_and_its_inverse(kind, n):
+    t = Forms()
+    assert np.array_equal(np.array(fwd(unit(n), kind, t)), M.transform_matrix(kind, n))
+    assert np.array_equal(np.array(inv(unit(n), kind, t)), 2 * M.scaled_inverse(kind, n))
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_zonal_path_fits_int32_for_full_range_int16(kind, n):
+    T = M.transform_matrix(kind, n)
+    row = peak(fwd, unit(n), kind)
+    col = row * np.abs(T).sum(1).max()
+    assert col * XMAX <= INT32
+    # every r for N = 8, 16; for N = 32 a stride through the range plus the
+    # levels where the inverse's intermediates peak
+    rs = range(1, n * n + 1) if n < 32 else sorted(set(range(1, 1025, 37)) |
+                                                    {172, 407, 692, 768, 1024})
+    worst = max(max(inverse_peaks(kind, n, mask(n, r))) for r in rs)
+    assert worst * XMAX <= INT32, worst
+    # the bound is tight enough to mean something: full retention needs 4 N^2
+    assert worst >= 4 * n * n
+
+
+def round_half_away(x):
+    return math.floor(abs(x) + 0.5) * (1 if x >= 0 else -1)
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [16, 32])
+def test_quantised_path_fits_int32_for_full_range_int16(kind, n):
+    # b~ = level * DQ = 2 rho b + e with rho = MQ DQ / 2^25 and |e| <= DQ / 2;
+    # the linear part has an exact bound, e is bounded term by term, and the
+    # column results are halved (exactly) before the row pass
+    T = M.transform_matrix(kind, n).astype(np.float64)
+    d = np.diag(T @ T.T)
+    forms = []
+
+    def collect(v):
+        forms.append(np.abs(v))
+        return v
+    outs = np.abs(np.array(inv(unit(n), kind, collect)))
+    W = np.array(forms)
+    for q in (1, 16, 4096):
+        g = q * np.sqrt(np.outer(d, d))
+        mq = np.vectorize(lambda x: round_half_away(2 ** 24 / x))(g)
+        dq = np.vectorize(lambda x: round_half_away(2 * x))(g)
+        rho = mq * dq / 2 ** 25
+        e = dq / 2
+        col_lin, _ = inverse_peaks(kind, n, 2 * rho)
+        _, row_lin = inverse_peaks(kind, n, rho)
+        col = col_lin * XMAX + (W @ e).max()
+        row = row_lin * XMAX + (W @ ((outs @ e) / 2 + 0.5).T).max()
+        assert max(col, row) <= INT32, (q, col, row)
+        # 24-bit products of the dequantiser are exact
+        bmax = np.abs(T).sum(1).max() ** 2 * XMAX
+        assert bmax * mq.max() / 2 ** 24 + 1 < 2 ** 23 and dq.max() < 2 ** 23
