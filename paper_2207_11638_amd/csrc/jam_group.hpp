@@ -275,11 +275,32 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
 // 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
 // LEVELS: S holds the quantisation levels already (no scaled output), so the
 // kept words are copied as they are.
+// With only the kept output and r >= BS, thread t owns zig-zag positions
+// t, t + BS, ... of every tile: it looks a position up once and walks the
+// tiles, each step a coalesced run of BS words across the threads (measured
+// +7 % on quantised int16 frames).  Otherwise consecutive threads take
+// consecutive (tile, position) elements (with the scaled output as a second
+// stream, the position-major order measured 5-13 % slower).
 template <int N, bool QUANT, bool LEVELS, int BS, int KB = N>
 __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh,
                                                const GroupIO& io) {
   using C = Cfg<N, BS, KB>;
   const int r = io.r;
+  if (r >= BS && io.scaled == nullptr) {
+    if (io.kept == nullptr) return;
+    uint32_t* kept = reinterpret_cast<uint32_t*>(io.kept);
+    for (int p = threadIdx.x; p < r; p += BS) {
+      const int w = sh.zz[p];
+      const int off = w & 0xffff;
+      const int32_t mq = QUANT && !LEVELS ? sh.mq[w >> 16] : 0;
+      int e = p;
+      for (int k = 0; k < io.nact; ++k, e += r) {
+        const int val = S[k * C::TS + off];
+        st_stream(kept + e, static_cast<uint32_t>(QUANT && !LEVELS ? quantise(val, mq) : val));
+      }
+    }
+    return;
+  }
   const int total = io.nact * r;
   if (threadIdx.x >= total) return;
   int k = threadIdx.x / r;
