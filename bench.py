@@ -144,7 +144,20 @@ def cpu_baseline(h, w, images=12):
     cpu_s = sum(t for t, _ in res)
     return {"value": px / wall / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{images} images of {h}x{w}, full T x r sweep ({len(tasks)} passes), "
-                      f"{cpu_s:.1f} s of CPU work in {wall:.1f} s wall"}
+                      f"{cpu_s:.1f} s of CPU work in {wall:.1f} s wall",
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    """The host CPU's model name (first processor entry), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ------------------------------------------------------------------ GPU leg

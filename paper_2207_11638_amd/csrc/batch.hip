@@ -10,10 +10,14 @@
 // thread for 16x16 and 32x32 TUs.  The retained coefficients of an item are
 // contiguous, so a group's outputs are written as one block.
 //
-// Run.  A run is: clear the per-image error energies, one launch per bucket
-// over all of its items (the hardware dispatcher balances the workgroups),
-// then the per-image PSNR.  The same sequence can be captured in a HIP graph
-// and replayed, or, as a baseline, issued as one launch per image and bucket.
+// Run.  A run is: clear the per-image error energies, the TU launches, then
+// the per-image PSNR.  The TU launches are either one per bucket over all of
+// its items (the hardware dispatcher balances the workgroups) or the unified
+// form: one launch per quantiser class whose items of every size are ordered
+// by image and position, so that TUs sharing pixel lines run together.  The
+// zonal class takes a row-per-thread form for every size when its kept
+// bounds allow it.  The tuned sequence can be captured in a HIP graph and
+// replayed, or, as a baseline, issued as one launch per image and bucket.
 //
 // Shape.  The workgroup size of every bucket (8x8: 64 or 256 threads; 16x16
 // and 32x32: 128 or 256) is chosen by adct_batch_tune, which times the
