@@ -218,7 +218,8 @@ typedef struct adct_batch adct_batch_t;
  * retained coefficients of all TUs are packed into one array of *kept_words
  * words: TU t owns words [tu_kept_offset[t], + min(r, n*n)) in zig-zag order
  * (tu_kept_offset may be NULL).  TUs may be given in any order; TUs of one
- * image must not overlap. */
+ * image must not overlap (ADCT_E_SHAPE otherwise, like a TU outside its
+ * image or not aligned to its size). */
 ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
                                const adct_tu_desc_t* tus, int64_t n_tus, int dtype,
                                int64_t* tu_kept_offset, int64_t* kept_words,

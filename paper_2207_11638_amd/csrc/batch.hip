@@ -745,6 +745,29 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
       return set_error(ADCT_E_SHAPE, msg);
     }
   }
+  // TUs of one image must not overlap (their reconstructions would race):
+  // one bit per 8x8 cell of every image, set by the TU that covers it
+  {
+    std::vector<int64_t> cell0(static_cast<size_t>(n_images) + 1, 0);
+    for (int i = 0; i < n_images; ++i)
+      cell0[i + 1] = cell0[i] + static_cast<int64_t>(images[i].height / 8) * (images[i].width / 8);
+    std::vector<uint64_t> used(static_cast<size_t>((cell0[n_images] + 63) / 64), 0);
+    for (int64_t t = 0; t < n_tus; ++t) {
+      const adct_tu_desc_t& u = tus[t];
+      const int64_t cw = images[u.image].width / 8;
+      for (int dy = 0; dy < u.n / 8; ++dy)
+        for (int dx = 0; dx < u.n / 8; ++dx) {
+          const int64_t c = cell0[u.image] + (u.y / 8 + dy) * cw + u.x / 8 + dx;
+          const uint64_t bit = 1ull << (c & 63);
+          if (used[c >> 6] & bit) {
+            snprintf(msg, sizeof(msg), "batch: TU %lld overlaps another TU of image %d",
+                     (long long)t, u.image);
+            return set_error(ADCT_E_SHAPE, msg);
+          }
+          used[c >> 6] |= bit;
+        }
+    }
+  }
   auto* b = new adct_batch();
   b->dtype = dtype;
   b->n_images = n_images;

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
 #pragma unroll
     for (int v = 0; v < N; ++v) c[v] >>= 1;
   }
-  write_column_rows<N, kBlock>(S, j, k, c);
+  write_inverse_column<N, kBlock>(S, j, k, c);
   __syncthreads();
   const int i = a_idx;
   int z[N];

@@ -154,6 +154,15 @@ def test_batch_plan_validation_before_gpu(lib):
     d2 = descs.copy(); d2[0]["src_offset"] = 4      # not 16-byte aligned
     assert create(d2, tus) == -3
     assert create(descs, tus, dtype=5) == -1
+    two = np.zeros(2, dtype=adct.TU_DESC)
+    two[0], two[1] = (0, 0, 0, 16), (0, 8, 8, 8)    # the 8x8 TU lies inside the 16x16 one
+    assert create(descs, two) == -2
+    assert "overlaps" in lib.adct_last_error().decode()
+    two[1] = (0, 16, 0, 8)                          # neighbours: validation passes
+    st = create(descs, two)
+    assert st in (0, -4)                            # -4: no device to build the plan on
+    if st == 0:
+        lib.adct_batch_destroy(h)
     assert lib.adct_batch_run(None, None, None, None, None, None, None, 0, None) == -1
 
 
