@@ -144,11 +144,6 @@ __global__ __launch_bounds__(jam::kBlock) void serve_jam(const SReq* reqs, const
   block_add_sse<jam::kBlock>(rq.sse, e, red);
 }
 
-__global__ void clear_u64(unsigned long long* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
-}
-
 // ------------------------------------------------------------- host side
 // Class of a request: requests of one class share one kernel.
 struct ClassKey {
@@ -191,12 +186,26 @@ struct Member {
   int table = 0;          // index in the batch's request table
 };
 
+// A batch's table travels as one block, in pinned host memory and on the
+// device: m request records, m first-item offsets, m error energies (zeros
+// on upload, so no fill kernel is needed), each part 16-byte aligned.
+struct TableLayout {
+  size_t begins, sse, bytes;
+};
+
+inline size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
+
+inline TableLayout table_layout(size_t m) {
+  TableLayout l;
+  l.begins = align16(m * sizeof(SReq));
+  l.sse = align16(l.begins + m * sizeof(int));
+  l.bytes = l.sse + m * sizeof(unsigned long long);
+  return l;
+}
+
 struct Slot {
-  SReq* d_reqs = nullptr;
-  int* d_begins = nullptr;
-  unsigned long long* d_sse = nullptr;
-  SReq* h_reqs = nullptr;
-  int* h_begins = nullptr;
+  char* d_table = nullptr;       // device copy of the batch table
+  char* h_table = nullptr;       // pinned host staging of the batch table
   unsigned long long* h_sse = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ready = nullptr;    // recorded on the caller's stream at flush
@@ -335,11 +344,9 @@ int ensure_device(adct_server* s) {
   for (int i = 0; i < s->max_inflight; ++i) {
     Slot& sl = s->slots[i];
     const size_t nb = s->max_batch;
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_reqs), nb * sizeof(SReq));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_begins), nb * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_sse), nb * 8);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_reqs), nb * sizeof(SReq), 0);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_begins), nb * sizeof(int), 0);
+    const size_t tb = table_layout(nb).bytes;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_table), tb);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_table), tb, 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_sse), nb * 8, 0);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming);
@@ -446,6 +453,13 @@ int do_flush(adct_server* s, int* launched) {
     ClassKey key;
     int first, count, items;
   };
+  const TableLayout lay = table_layout(m);
+  SReq* h_reqs = reinterpret_cast<SReq*>(sl.h_table);
+  int* h_begins = reinterpret_cast<int*>(sl.h_table + lay.begins);
+  memset(sl.h_table + lay.sse, 0, static_cast<size_t>(m) * sizeof(unsigned long long));
+  SReq* d_reqs = reinterpret_cast<SReq*>(sl.d_table);
+  const int* d_begins = reinterpret_cast<const int*>(sl.d_table + lay.begins);
+  auto* d_sse = reinterpret_cast<unsigned long long*>(sl.d_table + lay.sse);
   std::vector<Launch> launches;
   for (int t = 0; t < m; ++t) {
     Member& mb = sl.members[order[t]];
@@ -458,20 +472,20 @@ int do_flush(adct_server* s, int* launched) {
     const int tiles_x = q.width / q.n;
     const int tiles_y = q.height / q.n;
     const int gx = groups_x_of(q.n, tiles_x);
-    SReq& rec = sl.h_reqs[t];
+    SReq& rec = h_reqs[t];
     rec.src = q.d_src;
     rec.dst = s->arena + mb.off + mb.recon_off;
     rec.kept = reinterpret_cast<int32_t*>(s->arena + mb.off + mb.kept_off);
     rec.scaled = mb.scaled_off >= 0 ? reinterpret_cast<float*>(s->arena + mb.off + mb.scaled_off)
                                     : nullptr;
-    rec.sse = sl.d_sse + t;
+    rec.sse = d_sse + t;
     rec.pitch = q.pitch;
     rec.tiles_x = tiles_x;
     rec.groups_x = gx;
     rec.r = q.r;
     rec.pad = 0;
     rec.t = *tb;
-    sl.h_begins[t] = L.items;
+    h_begins[t] = L.items;
     L.items += gx * tiles_y;
     ++L.count;
     mb.table = t;
@@ -480,17 +494,15 @@ int do_flush(adct_server* s, int* launched) {
   const hipStream_t st = sl.stream;
   hipError_t e = hipEventRecord(sl.ready, s->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, sl.ready, 0);
+  // one upload: request records, first-item offsets and zeroed error energies
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, m * sizeof(SReq), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.d_begins, sl.h_begins, m * sizeof(int), hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(sl.d_table, sl.h_table, lay.bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "request table upload");
-  clear_u64<<<(m + 255) / 256, 256, 0, st>>>(sl.d_sse, m);
   for (const Launch& L : launches)
-    launch_class(L.key, L.items, st, sl.d_reqs + L.first, sl.d_begins + L.first, L.count);
+    launch_class(L.key, L.items, st, d_reqs + L.first, d_begins + L.first, L.count);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "class launch");
-  e = hipMemcpyAsync(sl.h_sse, sl.d_sse, m * 8, hipMemcpyDeviceToHost, st);
+  e = hipMemcpyAsync(sl.h_sse, d_sse, m * 8, hipMemcpyDeviceToHost, st);
   for (int i = 0; i < m && e == hipSuccess; ++i) {
     const Member& mb = sl.members[i];
     const adct_request_t& q = mb.req;
@@ -595,11 +607,8 @@ ADCT_API int adct_server_destroy(adct_server_t* s) {
   for (int id : s->inflight)
     if (hipEventSynchronize(s->slots[id].done) != hipSuccess) status = ADCT_E_HIP;
   for (Slot& sl : s->slots) {
-    if (sl.d_reqs) (void)hipFree(sl.d_reqs);
-    if (sl.d_begins) (void)hipFree(sl.d_begins);
-    if (sl.d_sse) (void)hipFree(sl.d_sse);
-    if (sl.h_reqs) (void)hipHostFree(sl.h_reqs);
-    if (sl.h_begins) (void)hipHostFree(sl.h_begins);
+    if (sl.d_table) (void)hipFree(sl.d_table);
+    if (sl.h_table) (void)hipHostFree(sl.h_table);
     if (sl.h_sse) (void)hipHostFree(sl.h_sse);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.ready) (void)hipEventDestroy(sl.ready);
