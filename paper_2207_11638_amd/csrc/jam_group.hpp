@@ -70,9 +70,38 @@ struct Shared {
   int32_t zz[N * N];
 };
 
-// Fill the tables of one workgroup.  The zonal part depends on r only; it
-// reads the row classes from the kernel argument, so no barrier is needed
-// before it.  The caller synchronises before the first use.
+// Inverse zig-zag scan of an N x N block: entry p is (v << 8) | u of the
+// coefficient at scan position p, built at compile time from zz_pos.
+template <int N>
+struct ZigzagInv {
+  uint16_t vu[N * N];
+};
+
+template <int N>
+constexpr ZigzagInv<N> make_zigzag_inv() {
+  ZigzagInv<N> z{};
+  for (int v = 0; v < N; ++v)
+    for (int u = 0; u < N; ++u) z.vu[zz_pos(N, v, u)] = static_cast<uint16_t>((v << 8) | u);
+  return z;
+}
+
+static __constant__ ZigzagInv<8> kZigzagInv8 = make_zigzag_inv<8>();
+static __constant__ ZigzagInv<16> kZigzagInv16 = make_zigzag_inv<16>();
+static __constant__ ZigzagInv<32> kZigzagInv32 = make_zigzag_inv<32>();
+
+template <int N>
+__device__ __forceinline__ int zigzag_inv(int p) {
+  if constexpr (N == 8) return kZigzagInv8.vu[p];
+  else if constexpr (N == 16) return kZigzagInv16.vu[p];
+  else return kZigzagInv32.vu[p];
+}
+
+// Fill the tables of one workgroup.  Thread p < r writes zig-zag entry p from
+// the inverse scan; thread u < N counts the kept rows of column u by
+// bisection (zz_pos(N, v, u) grows with v, so the kept rows are a prefix).
+// The tables depend on r and on the row classes, read from the kernel
+// argument, so no barrier is needed before this.  The caller synchronises
+// before the first use.
 template <int N, int BS>
 __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int r) {
   const int i = threadIdx.x;
@@ -81,15 +110,22 @@ __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int 
     sh.dq[i] = t.dq[i];
     sh.s2[i] = t.s2[i];
   }
-  if (i < N) sh.cls[i] = t.cls[i];
+  if (i < N) {
+    sh.cls[i] = t.cls[i];
+    int cnt = 0;   // largest cnt with zz_pos(N, cnt - 1, i) < r, by binary lifting
 #pragma unroll
-  for (int idx = i; idx < N * N; idx += BS) {
-    const int v = idx / N, u = idx % N;
-    const bool kept = zz_pos(N, v, u) < r;
-    const bool below_kept = v + 1 < N && zz_pos(N, v + 1, u) < r;
-    if (kept) sh.zz[zz_pos(N, v, u)] = (v * (N + 1) + u) | ((t.cls[v] * 4 + t.cls[u]) << 16);
-    if (kept && !below_kept) sh.cnt[u] = v + 1;
-    if (v == 0 && !kept) sh.cnt[u] = 0;
+    for (int step = N; step > 0; step >>= 1)
+      if (cnt + step <= N && zz_pos(N, cnt + step - 1, i) < r) cnt += step;
+    sh.cnt[i] = cnt;
+  }
+#pragma unroll
+  for (int q = 0; q < (N * N + BS - 1) / BS; ++q) {
+    const int p = i + q * BS;
+    if (p < r) {
+      const int vu = zigzag_inv<N>(p);
+      const int v = vu >> 8, u = vu & 0xff;
+      sh.zz[p] = (v * (N + 1) + u) | ((t.cls[v] * 4 + t.cls[u]) << 16);
+    }
   }
 }
 
@@ -286,7 +322,9 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
                                                const GroupIO& io) {
   using C = Cfg<N, BS, KB>;
   const int r = io.r;
-  if (r >= BS && io.scaled == nullptr) {
+  // largest r the kept bound allows; below BS the branch is not compiled
+  constexpr int kMaxR = KB == N ? N * N : KB * (KB + 1) / 2;
+  if (kMaxR >= BS && r >= BS && io.scaled == nullptr) {
     if (io.kept == nullptr) return;
     uint32_t* kept = reinterpret_cast<uint32_t*>(io.kept);
     for (int p = threadIdx.x; p < r; p += BS) {
