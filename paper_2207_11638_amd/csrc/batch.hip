@@ -271,13 +271,13 @@ __global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
 // LDS.  The launch then needs far less LDS and fewer registers per workgroup
 // than the general one, which holds 64 pixels per thread for its 8x8 TUs and
 // a full 32x32 exchange buffer, so more workgroups share a compute unit to
-// hide the latency of the short items.  An item holds 4 groups of 32 8x8
-// TUs (8 KB of pixels), 4 groups of 16 16x16 TUs (16 KB) or one group of 8
+// hide the latency of the short items.  An item holds 2 groups of 32 8x8
+// TUs (4 KB of pixels), 2 groups of 16 16x16 TUs (8 KB) or one group of 8
 // 32x32 TUs (8 KB), processed one group after the other with the tables
 // loaded once and one error-energy atomic per item.  The 32x32 item stays a
 // single group: the group loop would keep enough state live to cost 30
 // registers, and the launch's occupancy is set by its largest path.
-constexpr int kSmallGroups[3] = {4, 4, 1};   // groups per item, n = 8, 16, 32
+constexpr int kSmallGroups[3] = {2, 2, 1};   // groups per item, n = 8, 16, 32
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kSmallWords =
