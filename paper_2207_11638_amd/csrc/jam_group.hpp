@@ -341,9 +341,14 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
   }
   const int total = io.nact * r;
   if (threadIdx.x >= total) return;
-  int k = threadIdx.x / r;
+  // quotients by r through one approximate reciprocal: for t <= 256 and
+  // r <= 1024, (t + 1/2) / r lies at least 1/(2r) >= 2^-11 from an integer,
+  // far more than the few ulps of error of the reciprocal and the product,
+  // so the truncation is floor(t / r)
+  const float rr = __builtin_amdgcn_rcpf(static_cast<float>(r));
+  int k = static_cast<int>((static_cast<float>(threadIdx.x) + 0.5f) * rr);
   int p = threadIdx.x - k * r;
-  const int dk = BS / r, dp = BS - dk * r;
+  const int dk = static_cast<int>((static_cast<float>(BS) + 0.5f) * rr), dp = BS - dk * r;
   for (int e = threadIdx.x; e < total; e += BS) {
     const int w = sh.zz[p];
     const int val = S[k * C::TS + (w & 0xffff)];
