@@ -504,8 +504,11 @@ def run_c2(args):
     frames = args.images or 64
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(args.gen_workers, frames)) as wp:
-        planes = [p for fr in wp.map(_c2_frame, range(frames)) for p in fr]
+    if args.gen_workers <= 1:     # in-process (no fork after a profiler set up the GPU)
+        planes = [p for f in range(frames) for p in _c2_frame(f)]
+    else:
+        with mp.get_context("fork").Pool(min(args.gen_workers, frames)) as wp:
+            planes = [p for fr in wp.map(_c2_frame, range(frames)) for p in fr]
     npx = sum(p.size for p in planes)
     log(f"generated {frames} frames ({len(planes)} planes, {npx / 1e6:.0f} Mpx) in "
         f"{time.perf_counter() - t0:.1f} s")
