@@ -78,10 +78,13 @@ struct BucketParams {
   Tables t;
 };
 
-template <typename T>
-__device__ __forceinline__ T* offset_px(T* base, int64_t px, int esize) {
-  return base == nullptr ? nullptr
-                         : reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + px * esize);
+// Byte-pointer arithmetic (not an integer round trip), so that the compiler
+// still sees a global-memory pointer and emits global, not flat, accesses.
+__device__ __forceinline__ const void* offset_px(const void* base, int64_t px, int esize) {
+  return base == nullptr ? nullptr : static_cast<const char*>(base) + px * esize;
+}
+__device__ __forceinline__ void* offset_px(void* base, int64_t px, int esize) {
+  return base == nullptr ? nullptr : static_cast<char*>(base) + px * esize;
 }
 
 // Where a launch reads pixels and writes its outputs.
