@@ -97,11 +97,11 @@ __device__ __forceinline__ int zigzag_inv(int p) {
 }
 
 // Fill the tables of one workgroup.  Thread p < r writes zig-zag entry p from
-// the inverse scan; thread u < N counts the kept rows of column u by
-// bisection (zz_pos(N, v, u) grows with v, so the kept rows are a prefix).
-// The tables depend on r and on the row classes, read from the kernel
-// argument, so no barrier is needed before this.  The caller synchronises
-// before the first use.
+// the inverse scan; thread u < N counts the kept rows of column u by binary
+// lifting (zz_pos(N, v, u) grows with v, so the kept rows are a prefix).
+// The tables depend on r and on the row classes of `t` only, not on LDS, so
+// no barrier is needed before this.  The caller synchronises before the
+// first use.
 template <int N, int BS>
 __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int r) {
   const int i = threadIdx.x;
