@@ -119,32 +119,121 @@ def summarize_pmc(fetch_dir, write_dir):
                       "write_scale": wscale}))
 
 
+# ------------------------------------------------------------- host workers
+# Host-side work (drawing the synthetic inputs, timing the oracle) runs in
+# worker processes only while this process has not touched the GPU, and never
+# under a profiler: a process that has initialised the GPU (the profiler's
+# preloaded library does so at start-up) must not fork, and a pool torn down
+# with terminate() SIGTERMs its workers, which the profiler's chained signal
+# handler turns into an abort.  Pools here are therefore created before the
+# first GPU call and always shut down with close() + join(), so each worker
+# leaves through its normal exit path.  Everywhere else threads are used.
+_GPU_TOUCHED = False
+# worker processes on the GPU machine: its CPU share for one GPU, whatever the
+# host's core count is
+MAX_WORKERS = 16
+
+
+def under_profiler() -> bool:
+    """True when a rocprofv3 tool library is loaded into this process."""
+    return (any(k.startswith(("ROCPROF", "ROCP_")) for k in os.environ)
+            or "rocprof" in os.environ.get("LD_PRELOAD", ""))
+
+
+def host_workers(requested=None) -> int:
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:   # pragma: no cover
+        avail = os.cpu_count() or 1
+    n = min(avail, MAX_WORKERS)
+    return max(1, min(n, requested) if requested else n)
+
+
+def gpu_device():
+    """cuda:0, remembering that the process now uses the GPU."""
+    global _GPU_TOUCHED
+    import torch
+    _GPU_TOUCHED = True
+    return torch.device("cuda:0")
+
+
+class HostPool:
+    """map() over worker processes when that is safe (no GPU use yet, no
+    profiler), over threads otherwise; closed with close() + join()."""
+
+    def __init__(self, workers: int):
+        self.workers = max(1, workers)
+        if self.workers > 1 and not _GPU_TOUCHED and not under_profiler():
+            import multiprocessing as mp
+            self.kind = "processes"
+            self.pool = mp.get_context("fork").Pool(self.workers)
+        else:
+            from multiprocessing.pool import ThreadPool
+            self.kind = "threads"
+            self.pool = ThreadPool(self.workers)
+
+    def map(self, fn, items, chunksize=1):
+        return self.pool.map(fn, items, chunksize=chunksize)
+
+    def imap(self, fn, items, chunksize=1):
+        return self.pool.imap(fn, items, chunksize=chunksize)
+
+    def close(self):
+        self.pool.close()
+        self.pool.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _c1_image(i_hw):
+    import synth
+    i, h, w = i_hw
+    return synth.ar1_batch_image(i, h, w)[0]
+
+
+def c1_images(pool, b, h, w):
+    """Images 0..b-1 of the 2048^2 AR(1) batch (uint8 [b, h, w])."""
+    import numpy as np
+    imgs = np.empty((b, h, w), dtype=np.uint8)
+    for i, img in enumerate(pool.imap(_c1_image, [(i, h, w) for i in range(b)], chunksize=4)):
+        imgs[i] = img
+    return imgs
+
+
 # ------------------------------------------------------------------ CPU leg
 def _oracle_task(args):
-    img_seed, kind, r, h, w = args
-    import synth
+    """One oracle pass over one image; returns (seconds in the oracle, pixels)."""
+    img, kind, r = args
     from oracle import pipeline as P
-    img, _ = synth.ar1_batch_image(img_seed, h, w)
     t0 = time.perf_counter()
     P.compress(img, kind, N, r)
     return time.perf_counter() - t0, img.size
 
 
-def cpu_baseline(h, w, images=12):
-    """The oracle as it stands, over a bounded sample: the full 14-point sweep
-    on ``images`` images, one (image, T, r) task per worker process."""
-    import multiprocessing as mp
-    cores = min(16, os.cpu_count() or 1)
-    tasks = [(i, k, r, h, w) for i in range(images) for k in KINDS for r in SWEEP_R]
+def cpu_baseline(pool, sample):
+    """The oracle as it stands, timed on the host's cores over a bounded
+    sample: the full 14-point T x r sweep of ``sample`` (images drawn before
+    the timed region), one (image, T, r) pass per task.  ``value`` is pixels
+    over the wall time of the oracle passes; the summed time inside the oracle
+    is reported beside it."""
+    tasks = [(img, k, r) for img in sample for k in KINDS for r in SWEEP_R]
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_oracle_task, tasks, chunksize=1)
+    res = pool.map(_oracle_task, tasks)
     wall = time.perf_counter() - t0
     px = sum(p for _, p in res)
     cpu_s = sum(t for t, _ in res)
-    return {"value": px / wall / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"{images} images of {h}x{w}, full T x r sweep ({len(tasks)} passes), "
-                      f"{cpu_s:.1f} s of CPU work in {wall:.1f} s wall",
+    h, w = sample[0].shape
+    return {"value": px / wall / 1e9, "unit": "Gpixel/s", "cores": pool.workers,
+            "kind": "oracle",
+            "sample": f"{len(sample)} images of {h}x{w} from the same batch, full T x r sweep "
+                      f"({len(tasks)} passes, {px / 1e9:.2f} Gpx): {cpu_s:.1f} s inside the "
+                      f"oracle over {pool.workers} {pool.kind}, {wall:.2f} s wall",
+            "oracle_seconds": round(cpu_s, 2), "wall_seconds": round(wall, 3),
+            "workers": pool.kind, "host_cpus": os.cpu_count(),
             "cpu_model": cpu_model()}
 
 
@@ -168,15 +257,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("c0", "c1", "c2", "c3", "c4", "plain"), default="c1",
                     help="c0: latency of one 512^2 image; "
-                         "c1: the 1024 x 2048^2 sweep (default); c2: the int16 residual "
-                         "frames with 16/32-point transforms and quantisation; c3: the ragged "
-                         "batch; c4: the serving loop; "
+                         "c1: the 1024 x 2048^2 sweep (default; the line also carries the "
+                         "ragged batch against per-image launches and the serving latency); "
+                         "c2: the int16 residual frames with 16/32-point transforms and "
+                         "quantisation; c3: the ragged batch alone; c4: the serving loop alone; "
                          "plain: one fused configuration (--n, --transform, --r, --qstep)")
     ap.add_argument("--engine", choices=("butterfly", "mfma"), default="butterfly",
                     help="c1/plain: N=8 uint8 zonal passes on the butterflies or on the int8 "
                          "matrix cores")
     ap.add_argument("--rate", type=float, default=2000.0, help="c4: arrivals per second")
-    ap.add_argument("--duration", type=float, default=30.0, help="c4: trace length (s)")
+    ap.add_argument("--duration", type=float, default=None,
+                    help="c4: trace length in s (30 for --workload c4, 10 in the default line)")
     ap.add_argument("--pool", type=int, default=64, help="c4: device-resident images")
     ap.add_argument("--check-max", type=int, default=300,
                     help="c4: at most this many sampled requests checked against the oracle")
@@ -189,10 +280,16 @@ def main():
     ap.add_argument("--qstep", type=int, default=0)
     ap.add_argument("--dtype", choices=("u8", "i16"), default="u8")
     ap.add_argument("--images", type=int, default=None)
+    ap.add_argument("--c3-images", type=int, default=10000,
+                    help="c1 line: images of the ragged batch leg")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--c1-only", action="store_true",
+                    help="c1: time the sweep alone (no ragged-batch or serving leg)")
+    ap.add_argument("--gen-workers", type=int, default=None,
+                    help="host workers for input generation and the oracle (default: the "
+                         "CPUs available, at most 16; threads under a profiler)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy kernel first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -205,15 +302,21 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if under_profiler():
+        log("running under a profiler: host work uses threads, no worker processes")
 
     if args.workload == "c0":
         run_c0(args)
     elif args.workload == "c2":
         run_c2(args)
     elif args.workload == "c3":
-        run_c3(args)
+        with HostPool(host_workers(args.gen_workers)) as pool:
+            data = prepare_c3(args, pool, args.images or 10000)
+        print(json.dumps(c3_line(args, data, gpu_c3(args, data))), flush=True)
     elif args.workload == "c4":
-        run_c4(args)
+        with HostPool(host_workers(args.gen_workers)) as pool:
+            data = prepare_c4(args, pool, args.duration or 30.0)
+        print(json.dumps(c4_line(args, data, gpu_c4(args, data, sweep=True))), flush=True)
     elif args.workload == "plain":
         run_plain(args)
     else:
@@ -225,19 +328,51 @@ def log(msg):
 
 
 def run_c1(args):
+    """The default line: the C1 sweep, plus (unless --c1-only) the ragged batch
+    against per-image launches and the serving loop's p50/p99.  Every host
+    input and the oracle baseline are prepared before the GPU is touched."""
+    b, h, w = args.images or 1024, args.size, args.size
+    extras = not args.c1_only
+    t0 = time.perf_counter()
+    with HostPool(host_workers(args.gen_workers)) as pool:
+        imgs = c1_images(pool, b, h, w)
+        log(f"generated {b} images of {h}x{w} in {time.perf_counter() - t0:.1f} s "
+            f"({pool.workers} {pool.kind})")
+        cpu = None
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline(pool, [imgs[i] for i in range(min(4, b))])
+            log(f"CPU oracle: {cpu['value']:.3f} Gpx/s ({cpu['sample']})")
+        c3 = prepare_c3(args, pool, args.c3_images) if extras else None
+        c4 = prepare_c4(args, pool, args.duration or 10.0) if extras else None
+    line = gpu_c1(args, imgs, cpu)
+    if extras:
+        r3 = gpu_c3(args, c3)
+        line["batched_vs_plain"] = {
+            "workload": c3["workload"], "graph_ms": r3["graph_ms"],
+            "per_image_ms": r3["per_image_ms"], "speedup": r3["speedup"],
+            "graph_gpixel_s": r3["graph_gpixel_s"],
+            "per_image_gpixel_s": r3["per_image_gpixel_s"],
+            "graph_hbm_frac": r3["roofline"]["frac"], "kernel": r3["roofline"]["kernel"],
+            "parity_sample": r3["parity_sample"]}
+        r4 = gpu_c4(args, c4, sweep=False)
+        line["serving"] = {
+            "workload": c4["workload"], "p50_ms": r4["main"]["p50_ms"],
+            "p99_ms": r4["main"]["p99_ms"], "max_ms": r4["main"]["max_ms"],
+            "served_gpixel_s": r4["main"]["served_gpixel_s"],
+            "mean_batch": r4["main"]["mean_batch"], "parity_sample": r4["parity_sample"]}
+    print(json.dumps(line), flush=True)
+
+
+def gpu_c1(args, imgs, cpu):
     import numpy as np
     import torch
 
     import paper_2207_11638_amd as adct
     import synth
 
-    b, h, w = args.images or 1024, args.size, args.size
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    imgs, rhos = synth.ar1_batch(b, h, w, workers=args.gen_workers)
-    log(f"generated {b} images of {h}x{w} in {time.perf_counter() - t0:.1f} s")
+    b, h, w = imgs.shape
+    dev = gpu_device()
     x = torch.from_numpy(imgs).to(dev)
-    del imgs
     tiles = b * (h // N) * (w // N)
     rmax = max(SWEEP_R)
     kept_buf = torch.empty(tiles * rmax, dtype=torch.int32, device=dev)
@@ -276,6 +411,7 @@ def run_c1(args):
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
+    # events recorded on the current stream, the one the launches go to
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
            for _ in combos] for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
@@ -308,36 +444,38 @@ def run_c1(args):
 
     check = None
     if not args.no_check:
+        from concurrent.futures import ThreadPoolExecutor
+
         from oracle import pipeline as P
         k, r = 2, 10
         kv, sv = views(r)
         sse.zero_()
         adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse, engine=args.engine)
         torch.cuda.synchronize()
-        bad = 0
-        for i in sorted({0, b // 2, b - 1}):
-            img, _ = synth.ar1_batch_image(i, h, w)
-            want = P.compress(img, k, N, r)
-            bad += int(not np.array_equal(kv[i].cpu().numpy(), want["kept"]))
+        picks = sorted({0, b // 2, b - 1})
+
+        def one(i):
+            want = P.compress(imgs[i], k, N, r)
+            bad = int(not np.array_equal(kv[i].cpu().numpy(), want["kept"]))
             bad += int(not np.array_equal(recon[i].cpu().numpy(), want["recon"]))
             bad += int(int(sse[i].item()) != want["sse"])
             got_s = sv[i].cpu().numpy().astype(np.float64)
             nz = want["scaled"] != 0
+            bad += int(not np.all(got_s[~nz] == 0))
             bad += int(not np.all(np.abs(got_s[nz] - want["scaled"][nz])
                                   <= 1e-5 * np.abs(want["scaled"][nz])))
-        check = "ok" if bad == 0 else f"{bad} mismatches"
-        log(f"sampled parity vs oracle (T2, r=10, images 0, {b // 2}, {b - 1}): {check}")
+            return bad
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        cpu = cpu_baseline(h, w)
+        with ThreadPoolExecutor(len(picks)) as ex:
+            bad = sum(ex.map(one, picks))
+        check = "ok" if bad == 0 else f"{bad} mismatches"
+        log(f"sampled parity vs oracle (T2, r=10, images {picks}): {check}")
 
     traffic = measured_traffic() if args.engine == "butterfly" else None
     kernel = ("compress8 (fused 8x8 kernel; 14 instantiations, one per (T, r))"
               if args.engine == "butterfly" else
               "compress8_mfma (fused 8x8 kernel on the int8 matrix cores)")
-    out = {
+    return {
         "metric": METRIC,
         "value": round(value, 2),
         "unit": "Gpixel/s",
@@ -364,26 +502,26 @@ def run_c1(args):
         "parity_sample": check,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
 
 
 # ---------------------------------------------------------------- one config
 def run_plain(args):
     """One fused configuration over a batch of equal images (uint8 AR(1) or
     int16 Laplacian residuals), outputs kept + scaled + recon + sse."""
+    import numpy as np
     import torch
 
     import paper_2207_11638_amd as adct
     import synth
 
     b, h, w, n, r = args.images or 256, args.size, args.size, args.n, args.r
-    dev = torch.device("cuda:0")
     if args.dtype == "u8":
-        imgs, _ = synth.ar1_batch(b, h, w, workers=args.gen_workers)
-        x = torch.from_numpy(imgs).to(dev)
+        with HostPool(host_workers(args.gen_workers)) as pool:
+            imgs = c1_images(pool, b, h, w)
     else:
-        x = torch.stack([torch.from_numpy(synth.laplace_residual(h, w, seed=2000 + i))
-                         for i in range(b)]).to(dev)
+        imgs = np.stack([synth.laplace_residual(h, w, seed=2000 + i) for i in range(b)])
+    dev = gpu_device()
+    x = torch.from_numpy(imgs).to(dev)
     tiles = b * (h // n) * (w // n)
     kept = torch.empty((b, h // n, w // n, r), dtype=torch.int32, device=dev)
     scaled = torch.empty((b, h // n, w // n, r), dtype=torch.float32, device=dev)
@@ -434,8 +572,8 @@ def run_c0(args):
     import paper_2207_11638_amd as adct
     import synth
 
-    dev = torch.device("cuda:0")
     img = synth.ar1_image(512, 512, rho=0.95, sigma=40.0, seed=0)
+    dev = gpu_device()
     x = torch.from_numpy(img).to(dev)[None]
     reps = max(200, 50 * args.steps)
     res = {}
@@ -492,8 +630,6 @@ def run_c2(args):
     Heights 2160 and 1080 are not multiples of 32 (1080 not of 16): each
     plane is tiled by N x N units whose border strips are covered by the
     largest smaller TUs (the implicit split), through the TU-list path."""
-    import multiprocessing as mp
-
     import numpy as np
     import torch
 
@@ -502,13 +638,10 @@ def run_c2(args):
     from paper_2207_11638_amd import ragged
 
     frames = args.images or 64
-    dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    if args.gen_workers <= 1:     # in-process (no fork after a profiler set up the GPU)
-        planes = [p for f in range(frames) for p in _c2_frame(f)]
-    else:
-        with mp.get_context("fork").Pool(min(args.gen_workers, frames)) as wp:
-            planes = [p for fr in wp.map(_c2_frame, range(frames)) for p in fr]
+    with HostPool(host_workers(args.gen_workers)) as pool:
+        planes = [p for fr in pool.map(_c2_frame, range(frames)) for p in fr]
+    dev = gpu_device()
     npx = sum(p.size for p in planes)
     log(f"generated {frames} frames ({len(planes)} planes, {npx / 1e6:.0f} Mpx) in "
         f"{time.perf_counter() - t0:.1f} s")
@@ -631,24 +764,24 @@ def run_c2(args):
     print(json.dumps(out), flush=True)
 
 
-def run_c3(args):
-    """10000 images with log-normal sides in [64, 4096] (multiples of 8), AR(1)
-    content with rho ~ U[0.85, 0.98], each split by a seeded HEVC-style
-    quadtree (32x32 units, split probability 0.4 per level, forced splits at
-    the border) into 8/16/32 TUs; T1/T2 alternate by image, r ~ U{6..28} per
-    image.  One step = one pass over every TU (retained int32 coefficients,
-    reconstruction, error energy and PSNR per image).  Timed three ways: one
-    launch per bucket (the batched form), its graph replay, and one launch per
-    image and bucket (the per-image baseline)."""
+def _c3_image(job):
+    import synth
+    h, w, seed, rho = job
+    return synth.ar1_arena_image(h, w, seed, rho)
+
+
+def prepare_c3(args, pool, n):
+    """Host side of the ragged batch: n images with log-normal sides in
+    [64, 4096] (multiples of 8), AR(1) content with rho ~ U[0.85, 0.98], each
+    split by a seeded HEVC-style quadtree (32x32 units, split probability 0.4
+    per level, forced splits at the border) into 8/16/32 TUs; T1/T2 alternate
+    by image, r ~ U{6..28} per image."""
     import numpy as np
-    import torch
 
     import paper_2207_11638_amd as adct
     import synth
     from paper_2207_11638_amd import ragged
 
-    n = args.images or 10000
-    dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     sizes = synth.ragged_sizes(n, seed=3000)
     hs, ws = sizes[:, 0], sizes[:, 1]
@@ -661,8 +794,10 @@ def run_c3(args):
         offsets[i] = off
         off += int(pitches[i] * hs[i])
     total = (off + 255) // 256 * 256
-    arena = synth.ar1_arena(offsets, hs, ws, pitches, 3000 + np.arange(n), rhos, total,
-                            workers=args.gen_workers)
+    arena = np.zeros(total, dtype=np.uint8)
+    jobs = [(int(hs[i]), int(ws[i]), 3000 + i, float(rhos[i])) for i in range(n)]
+    for i, img in enumerate(pool.imap(_c3_image, jobs, chunksize=8)):
+        arena[offsets[i]:offsets[i] + pitches[i] * hs[i]].reshape(hs[i], pitches[i])[:, :ws[i]] = img
     rs = synth.rng_for(3002).integers(6, 29, size=n)
     descs = np.zeros(n, dtype=adct.IMAGE_DESC)
     descs["src_offset"] = offsets
@@ -674,14 +809,33 @@ def run_c3(args):
                                                    synth.rng_for(4_000_000 + i))
                            for i in range(n)])
     npx = int((hs * ws).sum())
-    log(f"generated {n} images ({npx / 1e9:.2f} Gpx) and {len(tus)} TUs in "
+    log(f"generated {n} ragged images ({npx / 1e9:.2f} Gpx) and {len(tus)} TUs in "
         f"{time.perf_counter() - t0:.1f} s")
+    return {"n": n, "arena": arena, "descs": descs, "tus": tus, "npx": npx, "hs": hs, "ws": ws,
+            "rs": rs, "offsets": offsets, "pitches": pitches,
+            "workload": f"ragged batch: {n} AR(1) images ({npx / 1e9:.2f} Gpx), sides "
+                        "log-normal in [64, 4096], 8/16/32 quadtree TUs (p=0.4), T1/T2, "
+                        "r in 6..28"}
+
+
+def gpu_c3(args, d):
+    """One step = one pass over every TU (retained int32 coefficients,
+    reconstruction, error energy and PSNR per image).  Timed four ways: one
+    launch per bucket, the unified launch, its graph replay (the batched
+    form), and one launch per image and bucket (the per-image baseline)."""
+    import numpy as np
+    import torch
+
+    import paper_2207_11638_amd as adct
+    from paper_2207_11638_amd import ragged
+
+    n, npx, descs, tus = d["n"], d["npx"], d["descs"], d["tus"]
+    dev = gpu_device()
     t0 = time.perf_counter()
     plan = adct.BatchPlan(descs, tus, torch.uint8)
     info = plan.info()
     log(f"plan built in {time.perf_counter() - t0:.1f} s: {info}")
-    src = torch.from_numpy(arena).to(dev)
-    del arena
+    src = torch.from_numpy(d["arena"]).to(dev)
     dst = torch.zeros_like(src)
     kept = torch.empty(max(1, plan.kept_words), dtype=torch.int32, device=dev)
     sse = torch.zeros(n, dtype=torch.uint64, device=dev)
@@ -719,72 +873,117 @@ def run_c3(args):
 
     check = None
     if not args.no_check:
+        from concurrent.futures import ThreadPoolExecutor
+
         from oracle import pipeline as P
-        plan.run(src, dst, kept, None, sse, psnr, mode="batched")
+        plan.run(src, dst, kept, None, sse, psnr, mode="graph")
         torch.cuda.synchronize()
         dst_h = dst.cpu().numpy()
         kept_h = kept.cpu().numpy()
         sse_h = sse.cpu().numpy().astype(np.int64)
-        bad = 0
-        for i in (0, n // 2, n - 1):
-            img = synth.ar1_arena([0], [hs[i]], [ws[i]], [ws[i]], [3000 + i], [rhos[i]],
-                                  int(hs[i] * ws[i])).reshape(hs[i], ws[i])
+        psnr_h = psnr.cpu().numpy().astype(np.float64)
+        arena = d["arena"]
+
+        def one(i):
+            h, w, o, pitch = (int(d[k][i]) for k in ("hs", "ws", "offsets", "pitches"))
+            img = arena[o:o + pitch * h].reshape(h, pitch)[:, :w]
             rec = ragged.unpack_image(dst_h, descs[i])
-            e = 0
+            bad = e = 0
             for t in np.nonzero(tus["image"] == i)[0]:
                 x, y, nn = int(tus[t]["x"]), int(tus[t]["y"]), int(tus[t]["n"])
-                r = min(int(rs[i]), nn * nn)
+                r = min(int(d["rs"][i]), nn * nn)
                 out = P.compress(img[y:y + nn, x:x + nn], int(descs[i]["transform"]), nn, r)
-                o = int(plan.tu_kept_offset[t])
-                bad += int(not np.array_equal(kept_h[o:o + r], out["kept"].reshape(-1)))
+                o_ = int(plan.tu_kept_offset[t])
+                bad += int(not np.array_equal(kept_h[o_:o_ + r], out["kept"].reshape(-1)))
                 bad += int(not np.array_equal(rec[y:y + nn, x:x + nn], out["recon"]))
                 e += out["sse"]
             bad += int(e != sse_h[i])
+            want_p = P.psnr(e, h * w)
+            bad += int(not (want_p == psnr_h[i] or
+                            abs(psnr_h[i] - want_p) <= 1e-5 * abs(want_p)))
+            return bad
+
+        picks = sorted({0, n // 2, n - 1})
+        with ThreadPoolExecutor(len(picks)) as ex:
+            bad = sum(ex.map(one, picks))
         check = "ok" if bad == 0 else f"{bad} mismatches"
-        log(f"sampled parity vs oracle (images 0, {n // 2}, {n - 1}, every TU): {check}")
+        log(f"sampled parity vs oracle (graph replay; images {picks}, every TU, error "
+            f"energy, PSNR): {check}")
 
     algo = 2 * npx + 4 * plan.kept_words + 12 * n
     achieved = algo / ms_graph / 1e6
-    out = {
-        "metric": METRIC,
-        "value": round(npx / ms_graph / 1e6, 2),
-        "unit": "Gpixel/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_graph, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (seeded ragged AR(1) uint8 images, quadtree TUs)",
-        "config": {"workload": f"ragged batch: {n} AR(1) images ({npx / 1e9:.2f} Gpx), sides "
-                               "log-normal in [64, 4096], 8/16/32 quadtree TUs (p=0.4), "
-                               "T1/T2, r in 6..28",
-                   "images": n, "tus": int(len(tus)), "pixels": npx},
-        "batched_vs_per_image": {"batched_ms": round(ms_batched, 3),
-                                 "unified_ms": round(ms_unified, 3),
-                                 "graph_ms": round(ms_graph, 3),
-                                 "per_image_ms": round(ms_per_image, 3),
-                                 "speedup": round(ms_per_image / ms_graph, 2),
-                                 "per_image_gpixel_s": round(npx / ms_per_image / 1e6, 2)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ("bucket_unified_small" if info.get("small_bound") else
-                                "bucket_unified") + " (graph replay of one launch over all "
-                               "buckets, XCD-sliced item order)"},
-        "plan": info,
-        "tuned_block_sizes": chosen.tolist(),
-        "parity_sample": check,
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+    return {"batched_ms": round(ms_batched, 3), "unified_ms": round(ms_unified, 3),
+            "graph_ms": round(ms_graph, 3), "per_image_ms": round(ms_per_image, 3),
+            "speedup": round(ms_per_image / ms_graph, 2),
+            "graph_gpixel_s": round(npx / ms_graph / 1e6, 2),
+            "per_image_gpixel_s": round(npx / ms_per_image / 1e6, 2),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": None,
+                         "kernel": ("bucket_unified_small" if info.get("small_bound") else
+                                    "bucket_unified") + " (graph replay of one launch over all "
+                                   "buckets, XCD-sliced item order)"},
+            "plan": info, "tuned_block_sizes": chosen.tolist(), "parity_sample": check}
 
+
+def c3_line(args, d, r):
+    return {
+        "metric": METRIC, "value": r["graph_gpixel_s"], "unit": "Gpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["graph_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded ragged AR(1) uint8 images, quadtree TUs)",
+        "config": {"workload": d["workload"], "images": d["n"], "tus": int(len(d["tus"])),
+                   "pixels": d["npx"]},
+        "batched_vs_per_image": {k: r[k] for k in ("batched_ms", "unified_ms", "graph_ms",
+                                                   "per_image_ms", "speedup",
+                                                   "per_image_gpixel_s")},
+        "roofline": r["roofline"], "plan": r["plan"], "tuned_block_sizes": r["tuned_block_sizes"],
+        "parity_sample": r["parity_sample"], "cpu_baseline": None}
 
 
 # -------------------------------------------------------------------- serving
+def _c4_image(job):
+    import synth
+    h, w, seed, rho = job
+    return synth.ar1_arena_image(h, w, seed, rho)
+
+
+def prepare_c4(args, pool, duration):
+    """Host side of the serving loop: a Poisson trace at --rate requests/s for
+    ``duration`` s (seed 4000); each request is one image from a pool of
+    --pool AR(1) images (sides log-normal around 1024 in [64, 4096],
+    multiples of 32) with its own T in {T1, T2}, N in {8, 16, 32} and
+    r in 6..28."""
+    import numpy as np
+
+    import synth
+
+    n_req = int(args.rate * duration)
+    trace = synth.serving_requests(n_req, seed=4000, rate_hz=args.rate)
+    pool_n = min(args.pool, n_req)
+    sizes = np.array([(t["h"], t["w"]) for t in trace[:pool_n]], dtype=np.int64)
+    px = sizes[:, 0] * sizes[:, 1]
+    offsets = np.concatenate([[0], np.cumsum(px)[:-1]]).astype(np.int64)
+    jobs = [(int(sizes[i, 0]), int(sizes[i, 1]), 5000 + i, 0.85 + 0.13 * ((i * 0.618) % 1.0))
+            for i in range(pool_n)]
+    t0 = time.perf_counter()
+    arena = np.zeros(int(px.sum()), dtype=np.uint8)
+    for i, img in enumerate(pool.imap(_c4_image, jobs)):
+        arena[offsets[i]:offsets[i] + px[i]] = img.reshape(-1)
+    log(f"serving pool of {pool_n} images ({px.sum() / 1e6:.1f} Mpx) generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    sweep = []
+    for rate in [float(v) for v in args.sweep.split(",") if v.strip()]:
+        sweep.append((rate, synth.serving_requests(int(rate), seed=4001, rate_hz=rate)))
+    return {"trace": trace, "n_req": n_req, "duration": duration, "pool_n": pool_n,
+            "sizes": sizes, "px": px, "offsets": offsets, "arena": arena, "sweep": sweep,
+            "workload": f"serving: Poisson {args.rate:.0f} req/s for {duration:.0f} s "
+                        f"({n_req} requests), sides log-normal (median 1024) in [64, 4096], "
+                        f"T1/T2, N in {{8,16,32}}, r in 6..28, {args.budget_gb:.0f} GB budget"}
+
+
 def _c4_check(task):
-    """Oracle check of one served request (worker process)."""
+    """Oracle check of one served request."""
     import numpy as np
 
     from oracle import pipeline as P
@@ -794,46 +993,28 @@ def _c4_check(task):
             and np.array_equal(recon, want["recon"]) and int(sse) == want["sse"])
 
 
-def run_c4(args):
-    """Serving loop: Poisson arrivals at --rate requests/s for --duration s
-    (seed 4000); each request is one image from a pool of --pool
-    device-resident AR(1) images (sides log-normal around 1024 in [64, 4096],
-    multiples of 32) with its own T in {T1, T2}, N in {8, 16, 32} and
-    r in 6..28, compressed with kept int32 + recon + error energy.  The trace
-    is replayed in real time by the library's native loop (admission by a
-    32 GB budget, continuous batching over two batch slots).  Reports p50/p99
-    latency (arrival to completion event) and served Gpixel/s, checks a
-    sample of >= 1 % of the requests (at most --check-max) against the oracle,
-    and sweeps higher arrival rates towards saturation."""
-    import multiprocessing as mp
-
+def gpu_c4(args, d, sweep):
+    """Replays the trace in real time through the library's native loop
+    (admission by the HBM budget, continuous batching over two batch slots).
+    Reports p50/p99 latency (arrival to completion event) and served
+    Gpixel/s, checks a sample of >= 1 % of the requests (at most --check-max)
+    against the oracle, and with ``sweep`` raises the arrival rate towards
+    saturation and times the same saturating requests issued one plain
+    adct_compress call each."""
     import numpy as np
     import torch
 
     import paper_2207_11638_amd as adct
-    import synth
 
-    dev = torch.device("cuda:0")
-    n_req = int(args.rate * args.duration)
-    trace = synth.serving_requests(n_req, seed=4000, rate_hz=args.rate)
-    pool_n = min(args.pool, n_req)
-    sizes = np.array([(t["h"], t["w"]) for t in trace[:pool_n]], dtype=np.int64)
-    px = sizes[:, 0] * sizes[:, 1]
-    offsets = np.concatenate([[0], np.cumsum(px)[:-1]])
-    seeds = [5000 + i for i in range(pool_n)]
-    rhos = [0.85 + 0.13 * ((i * 0.618) % 1.0) for i in range(pool_n)]
-    t0 = time.perf_counter()
-    arena = synth.ar1_arena(offsets, sizes[:, 0], sizes[:, 1], sizes[:, 1], seeds, rhos,
-                            int(px.sum()), workers=args.gen_workers)
-    log(f"pool of {pool_n} images ({px.sum() / 1e6:.1f} Mpx) generated in "
-        f"{time.perf_counter() - t0:.1f} s")
+    trace, n_req, pool_n = d["trace"], d["n_req"], d["pool_n"]
+    sizes, px, offsets, arena = d["sizes"], d["px"], d["offsets"], d["arena"]
+    dev = gpu_device()
     d_arena = torch.from_numpy(arena).to(dev)
     pool = [d_arena[int(o):int(o) + int(p)].view(int(h), int(w))
             for o, p, (h, w) in zip(offsets, px, sizes)]
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream
     budget = int(args.budget_gb * (1 << 30))
-
     pool_ptr = np.array([int(x.data_ptr()) for x in pool], dtype=np.uint64)
 
     def build(trace_, sample_every):
@@ -879,16 +1060,21 @@ def run_c4(args):
                "batches": int(st["batches"]), "largest_batch": int(st["max_batch"]),
                "mean_batch": round(len(trace_) / max(1, st["batches"]), 2),
                "budget_waits": int(st["refused"])}
-        return res, checks, sse
+        return res, checks, sse, lat
 
-    main_res, checks, sse = replay(trace, args.rate,
-                                   sample_every=max(1, min(100, n_req // max(1, args.check_max))))
+    main_res, checks, sse, lat = replay(
+        trace, args.rate, sample_every=max(1, min(100, n_req // max(1, args.check_max))))
+    slow = np.argsort(lat)[-3:][::-1]
+    main_res["slowest"] = [{"request": int(i), "arrival_ms": round(trace[i]["t"] * 1e3, 3),
+                            "latency_ms": round(float(lat[i]), 3)} for i in slow]
     log(f"served {n_req} requests at {args.rate:.0f}/s: p50 {main_res['p50_ms']} ms, "
-        f"p99 {main_res['p99_ms']} ms, {main_res['served_gpixel_s']} Gpx/s, "
-        f"{main_res['batches']} batches")
+        f"p99 {main_res['p99_ms']} ms, max {main_res['max_ms']} ms, "
+        f"{main_res['served_gpixel_s']} Gpx/s, {main_res['batches']} batches; slowest "
+        f"{main_res['slowest']}")
 
     check = None
     if not args.no_check:
+        from concurrent.futures import ThreadPoolExecutor
         tasks = []
         for i, j, hk, hr in checks:
             t = trace[i]
@@ -896,51 +1082,85 @@ def run_c4(args):
                                                                           int(sizes[j, 1]))
             tasks.append((img, t["transform"], t["n"], t["r"], hk.numpy().copy(),
                           hr.numpy().copy(), int(sse[i])))
-        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as wp:
-            good = wp.map(_c4_check, tasks, chunksize=1)
+        with ThreadPoolExecutor(host_workers(args.gen_workers)) as ex:
+            good = list(ex.map(_c4_check, tasks))
         check = "ok" if all(good) else f"{len(good) - sum(good)} of {len(good)} mismatches"
         log(f"oracle check of {len(tasks)} sampled requests ({100 * len(tasks) / n_req:.1f} %): "
             f"{check}")
 
-    sweep = []
-    for rate in [float(v) for v in args.sweep.split(",") if v.strip()]:
-        m = int(rate * 1.0)
-        tr = synth.serving_requests(m, seed=4001, rate_hz=rate)
-        res, _, _ = replay(tr, rate)
-        sweep.append(res)
-        log(f"sweep {rate:.0f}/s: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms, "
-            f"served {res['served_gpixel_s']} of offered {res['offered_gpixel_s']} Gpx/s, "
-            f"mean batch {res['mean_batch']}")
-        if res["served_gpixel_s"] < 0.8 * res["offered_gpixel_s"]:
-            break
+    sweep_res = []
+    plain = None
+    if sweep:
+        for rate, tr in d["sweep"]:
+            res, _, _, _ = replay(tr, rate)
+            sweep_res.append(res)
+            log(f"sweep {rate:.0f}/s: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms, "
+                f"served {res['served_gpixel_s']} of offered {res['offered_gpixel_s']} Gpx/s, "
+                f"mean batch {res['mean_batch']}")
+            if res["served_gpixel_s"] < 0.8 * res["offered_gpixel_s"]:
+                break
+        if d["sweep"]:
+            plain = plain_per_request(d["sweep"][-1][1][:20000], pool, sizes, pool_n)
+            log(f"the same requests as one plain adct_compress call each: "
+                f"{plain['gpixel_s']} Gpx/s ({plain['requests']} requests in "
+                f"{plain['seconds']} s)")
+    return {"main": main_res, "sweep": sweep_res, "plain_per_request": plain,
+            "parity_sample": check}
 
-    out = {
-        "metric": METRIC,
-        "value": main_res["served_gpixel_s"],
-        "unit": "Gpixel/s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 0,
-        "ms_per_step": round(args.duration * 1e3, 1),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
+
+def plain_per_request(trace_, pool, sizes, pool_n):
+    """Every request of a saturating trace as its own adct_compress call (the
+    fused plain pipeline, outputs kept + recon + error energy), issued back to
+    back on one stream through the C ABI: the unbatched baseline of the
+    serving loop at saturation."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2207_11638_amd import _lib
+    lib = _lib.load()
+    dev = pool[0].device
+    m = len(trace_)
+    j = np.arange(m) % pool_n
+    words = max((int(sizes[j[i], 0]) // t["n"]) * (int(sizes[j[i], 1]) // t["n"]) * t["r"]
+                for i, t in enumerate(trace_))
+    kept = torch.empty(words, dtype=torch.int32, device=dev)
+    recon = torch.empty(int((sizes[:, 0] * sizes[:, 1]).max()), dtype=torch.uint8, device=dev)
+    sse = torch.zeros(1, dtype=torch.uint64, device=dev)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    calls = []
+    for i, t in enumerate(trace_):
+        x = pool[j[i]]
+        h, w = int(sizes[j[i], 0]), int(sizes[j[i], 1])
+        calls.append((t["transform"], t["n"], t["r"], 0, C.c_void_p(x.data_ptr()), 0, 1, h, w,
+                      w, h * w, C.c_void_p(kept.data_ptr()), None, C.c_void_p(recon.data_ptr()),
+                      C.c_void_p(sse.data_ptr()), stream))
+    fn = lib.adct_compress
+    for c in calls[:100]:
+        fn(*c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in calls:
+        if fn(*c) != 0:
+            _lib.check(-4)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    npx = int(sum(int(sizes[j[i], 0]) * int(sizes[j[i], 1]) for i in range(m)))
+    return {"requests": m, "seconds": round(sec, 3), "gpixel_s": round(npx / sec / 1e9, 3)}
+
+
+def c4_line(args, d, r):
+    main = r["main"]
+    return {
+        "metric": METRIC, "value": main["served_gpixel_s"], "unit": "Gpixel/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(d["duration"] * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Poisson trace, pool of AR(1) uint8 images)",
-        "config": {"workload": f"serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s "
-                               f"({n_req} requests), sides log-normal (median 1024) in "
-                               f"[64, 4096], T1/T2, N in {{8,16,32}}, r in 6..28, "
-                               f"{args.budget_gb:.0f} GB budget",
-                   "pool_images": pool_n},
-        "latency_ms": {"p50": main_res["p50_ms"], "p99": main_res["p99_ms"],
-                       "max": main_res["max_ms"]},
-        "serving": main_res,
-        "sweep": sweep,
-        "roofline": None,
-        "parity_sample": check,
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+        "config": {"workload": d["workload"], "pool_images": d["pool_n"]},
+        "latency_ms": {"p50": main["p50_ms"], "p99": main["p99_ms"], "max": main["max_ms"]},
+        "serving": main, "sweep": r["sweep"], "plain_per_request": r["plain_per_request"],
+        "roofline": None, "parity_sample": r["parity_sample"], "cpu_baseline": None}
 
 
 if __name__ == "__main__":

@@ -33,6 +33,7 @@ __all__ = [
     "quadtree_tus",
     "quadtree_tus_fast",
     "ar1_arena",
+    "ar1_arena_image",
     "ragged_sizes",
     "poisson_arrivals",
     "serving_requests",
@@ -61,14 +62,31 @@ def _ar1_along_rows(w: np.ndarray, rho: float) -> np.ndarray:
 
 
 def _ar1_along_columns(w: np.ndarray, rho: float) -> np.ndarray:
-    """The same recursion down the columns (axis 0), one image row at a time."""
+    """The same recursion down the columns (axis 0): y[0] = w[0] exactly, then
+    the filter runs over rows 1.. with its state started at rho*y[0].  It is
+    evaluated on the transposed field so that the filter walks contiguous
+    memory; the arithmetic per sample is the recursion's own
+    (rho*y[n-1] + c*w[n]), so the result does not depend on the layout."""
     c = np.sqrt(1.0 - rho * rho)
-    y = np.empty_like(w)
-    y[0] = w[0]
-    for n in range(1, w.shape[0]):
-        np.multiply(y[n - 1], rho, out=y[n])
-        y[n] += c * w[n]
-    return y
+    wt = np.ascontiguousarray(w.T)
+    yt = np.empty_like(wt)
+    yt[:, 0] = wt[:, 0]
+    if wt.shape[1] > 1:
+        yt[:, 1:], _ = lfilter([c], [1.0, -rho], wt[:, 1:], axis=1,
+                               zi=(rho * wt[:, 0])[:, None])
+    return yt.T
+
+
+def _to_u8(y: np.ndarray, sigma: float, mean: float) -> np.ndarray:
+    """clip(round(mean + sigma*y), 0, 255) as uint8, with round half away from
+    zero.  Every value that survives the clip is >= 0, where that rounding is
+    floor(t + 1/2); negative values clip to 0 either way."""
+    t = y * sigma
+    t += mean
+    t += 0.5
+    np.floor(t, out=t)
+    np.clip(t, 0, 255, out=t)
+    return t.astype(np.uint8)
 
 
 def ar1_field(h: int, w: int, rho: float, rng: np.random.Generator) -> np.ndarray:
@@ -82,9 +100,7 @@ def ar1_image(h: int, w: int, rho: float = 0.95, sigma: float = 40.0,
               mean: float = 128.0, seed: int = 0) -> np.ndarray:
     """uint8 image: clip(round(mean + sigma*field), 0, 255)."""
     rng = rng_for(seed)
-    y = ar1_field(h, w, rho, rng)
-    img = np.clip(_round_half_away(mean + sigma * y), 0, 255)
-    return img.astype(np.uint8)
+    return _to_u8(ar1_field(h, w, rho, rng), sigma, mean)
 
 
 def ar1_batch_image(i: int, h: int, w: int, seed_base: int = 1000,
@@ -97,56 +113,38 @@ def ar1_batch_image(i: int, h: int, w: int, seed_base: int = 1000,
     """
     rng = rng_for(seed_base + i)
     rho = float(rng.uniform(rho_lo, rho_hi))
-    y = ar1_field(h, w, rho, rng)
-    img = np.clip(_round_half_away(mean + sigma * y), 0, 255).astype(np.uint8)
-    return img, rho
-
-
-def _fill_ar1(args):
-    name, shape, lo, hi, kw = args
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(name=name)
-    try:
-        out = np.ndarray(shape, dtype=np.uint8, buffer=shm.buf)
-        rhos = []
-        for i in range(lo, hi):
-            out[i], rho = ar1_batch_image(i, shape[1], shape[2], **kw)
-            rhos.append(rho)
-        del out
-        return lo, rhos
-    finally:
-        shm.close()
+    return _to_u8(ar1_field(h, w, rho, rng), sigma, mean), rho
 
 
 def ar1_batch(n: int, h: int, w: int, workers: int = 1, **kw):
     """Images 0..n-1 of ``ar1_batch_image`` as one (n, h, w) uint8 array.
 
-    With ``workers`` > 1 the images are drawn in worker processes into shared
-    memory; the content does not depend on the worker count.  Returns
-    ``(images, rhos)``.
+    With ``workers`` > 1 the images are drawn by that many threads (NumPy and
+    SciPy release the interpreter lock in the heavy steps); no process is
+    forked, so this is safe in a process that already uses the GPU.  The
+    content does not depend on the worker count.  Returns ``(images, rhos)``.
     """
-    if workers <= 1 or n < 2:
-        imgs = np.empty((n, h, w), dtype=np.uint8)
-        rhos = []
-        for i in range(n):
-            imgs[i], rho = ar1_batch_image(i, h, w, **kw)
-            rhos.append(rho)
-        return imgs, np.array(rhos)
-    import multiprocessing as mp
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(create=True, size=n * h * w)
-    try:
-        chunk = max(1, n // (workers * 4))
-        jobs = [(shm.name, (n, h, w), lo, min(n, lo + chunk), kw) for lo in range(0, n, chunk)]
-        rhos = np.zeros(n)
-        with mp.get_context("fork").Pool(workers) as pool:
-            for lo, rr in pool.imap_unordered(_fill_ar1, jobs):
-                rhos[lo:lo + len(rr)] = rr
-        imgs = np.ndarray((n, h, w), dtype=np.uint8, buffer=shm.buf).copy()
-        return imgs, rhos
-    finally:
-        shm.close()
-        shm.unlink()
+    imgs = np.empty((n, h, w), dtype=np.uint8)
+    rhos = np.zeros(n)
+
+    def one(i):
+        imgs[i], rhos[i] = ar1_batch_image(i, h, w, **kw)
+
+    _run_threads(one, range(n), workers)
+    return imgs, rhos
+
+
+def _run_threads(fn, items, workers: int):
+    """fn(item) for every item, on ``workers`` threads (in order when 1)."""
+    items = list(items)
+    if workers <= 1 or len(items) < 2:
+        for it in items:
+            fn(it)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for _ in ex.map(fn, items):
+            pass
 
 
 def laplace_residual(h: int, w: int, scale: float = 12.0, clip: int = 255,
@@ -237,50 +235,28 @@ def quadtree_tus_fast(h: int, w: int, rng: np.random.Generator, p_split: float =
     return np.concatenate(out).astype(np.int32)
 
 
-def _fill_images(args):
-    name, total, jobs = args
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(name=name)
-    try:
-        arena = np.ndarray((total,), dtype=np.uint8, buffer=shm.buf)
-        for off, h, w, pitch, seed, rho in jobs:
-            rng = rng_for(seed)
-            y = ar1_field(h, w, rho, rng)
-            img = np.clip(_round_half_away(128.0 + 40.0 * y), 0, 255).astype(np.uint8)
-            arena[off:off + pitch * h].reshape(h, pitch)[:, :w] = img
-        del arena
-        return len(jobs)
-    finally:
-        shm.close()
+def ar1_arena_image(h: int, w: int, seed: int, rho: float) -> np.ndarray:
+    """One image of an arena: AR(1) field from ``seed`` with ``rho``, sigma 40,
+    mean 128, as uint8 (h x w)."""
+    return _to_u8(ar1_field(h, w, rho, rng_for(seed)), 40.0, 128.0)
 
 
 def ar1_arena(offsets, heights, widths, pitches, seeds, rhos, total: int, workers: int = 1):
     """Fill a flat uint8 arena with AR(1) images (sigma 40, mean 128) at the
     given pixel offsets, image i drawn from seed ``seeds[i]`` with ``rhos[i]``.
-    Padding between rows and images is zero."""
+    Padding between rows and images is zero.  ``workers`` > 1 draws the
+    images on that many threads (no process is forked)."""
     jobs = list(zip(map(int, offsets), map(int, heights), map(int, widths), map(int, pitches),
                     map(int, seeds), map(float, rhos)))
-    if workers <= 1:
-        arena = np.zeros(total, dtype=np.uint8)
-        for off, h, w, pitch, seed, rho in jobs:
-            y = ar1_field(h, w, rho, rng_for(seed))
-            img = np.clip(_round_half_away(128.0 + 40.0 * y), 0, 255).astype(np.uint8)
-            arena[off:off + pitch * h].reshape(h, pitch)[:, :w] = img
-        return arena
-    import multiprocessing as mp
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(create=True, size=max(1, total))
-    try:
-        np.ndarray((total,), dtype=np.uint8, buffer=shm.buf)[:] = 0
-        # largest images first so that the pool stays balanced
-        order = sorted(range(len(jobs)), key=lambda i: -jobs[i][1] * jobs[i][2])
-        chunks = [[jobs[i] for i in order[k::workers * 8]] for k in range(workers * 8)]
-        with mp.get_context("fork").Pool(workers) as pool:
-            pool.map(_fill_images, [(shm.name, total, c) for c in chunks if c])
-        return np.ndarray((total,), dtype=np.uint8, buffer=shm.buf).copy()
-    finally:
-        shm.close()
-        shm.unlink()
+    arena = np.zeros(total, dtype=np.uint8)
+
+    def one(job):
+        off, h, w, pitch, seed, rho = job
+        arena[off:off + pitch * h].reshape(h, pitch)[:, :w] = ar1_arena_image(h, w, seed, rho)
+
+    # largest images first so that the threads stay balanced
+    _run_threads(one, sorted(jobs, key=lambda j: -j[1] * j[2]), workers)
+    return arena
 
 
 def ragged_sizes(n: int, seed: int, median: float = 512.0, sigma: float = 0.75,

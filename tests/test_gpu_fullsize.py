@@ -3,6 +3,8 @@ benchmark times: sampled outputs checked one by one against the oracle (which
 computes a single tile, TU or request in milliseconds), plus exact properties
 checked on every image (the error energy of each image against its
 reconstruction, recomputed from scratch)."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -39,21 +41,45 @@ def check_scaled(got, want):
 
 @pytest.fixture(scope="module")
 def c1_images():
+    # drawn on threads: this process already uses the GPU, so it never forks
     imgs, _ = synth.ar1_batch(1024, 2048, 2048, workers=WORKERS)
     return imgs
 
 
-@pytest.mark.parametrize("kind,r", [(1, 10), (2, 45), (2, 64)])
-def test_c1_full_size_sampled_tiles(c1_images, kind, r):
-    # 1024 x 2048^2 uint8, N = 8: the launch the benchmark times
+def c1_spread(r):
+    # images interleaved by the fused 8x8 kernel's dispatch order for this r
+    return 64 if r <= 16 else (16 if r <= 45 else 2)
+
+
+def oracle_images(imgs, picks, kind, r):
+    with ThreadPoolExecutor(len(picks)) as ex:
+        return list(ex.map(lambda i: P.compress(imgs[i], kind, 8, r), picks))
+
+
+@pytest.mark.parametrize("kind", (1, 2))
+@pytest.mark.parametrize("r", (1, 6, 10, 16, 28, 45, 64))
+def test_c1_full_size(c1_images, kind, r):
+    # 1024 x 2048^2 uint8, N = 8: the launch the benchmark times.  Whole
+    # images spread over the interleave blocks (first, last of the first
+    # block, first of the second, last) against the oracle, sampled tiles
+    # of the others, and every image's error energy against its own
+    # reconstruction
     x = torch.from_numpy(c1_images).to(DEV)
     out = adct.compress(x, kind, 8, r)
     torch.cuda.synchronize()
     sse = out["sse"].cpu().numpy().astype(np.int64)
     assert np.array_equal(sse, exact_sse(x, out["recon"]))
-    rng = synth.rng_for(100 + r)
-    picks = np.stack([rng.integers(0, 1024, 200), rng.integers(0, 256, 200),
-                      rng.integers(0, 256, 200)], axis=1)
+    s = c1_spread(r)
+    picks = sorted({0, s - 1, s, 1023})
+    wants = oracle_images(c1_images, picks, kind, r)
+    for i, want in zip(picks, wants):
+        assert np.array_equal(out["kept"][i].cpu().numpy(), want["kept"]), i
+        check_scaled(out["scaled"][i].cpu().numpy(), want["scaled"])
+        assert np.array_equal(out["recon"][i].cpu().numpy(), want["recon"]), i
+        assert sse[i] == want["sse"], i
+    rng = synth.rng_for(100 + r + 1000 * kind)
+    picks = np.stack([rng.integers(0, 1024, 100), rng.integers(0, 256, 100),
+                      rng.integers(0, 256, 100)], axis=1)
     idx = torch.from_numpy(picks).to(DEV)
     kept = out["kept"][idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
     scaled = out["scaled"][idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
@@ -67,23 +93,30 @@ def test_c1_full_size_sampled_tiles(c1_images, kind, r):
     if r == 64:
         # full retention reconstructs every image exactly
         assert torch.equal(out["recon"], x) and sse.sum() == 0
+    del out, x
+    torch.cuda.empty_cache()
 
 
 def _frame(f):
     return synth.residual_frame_planes(f)
 
 
-def test_c2_full_size_sampled_tus():
-    # 64 residual frames, N = 32, T2, Q = 16, every coefficient quantised,
-    # implicit split at the 2160 / 1080 borders: the TU-list launch the
-    # benchmark times (tuned per-bucket sequence)
-    import multiprocessing as mp
-    with mp.get_context("fork").Pool(WORKERS) as wp:
-        planes = [p for fr in wp.map(_frame, range(64)) for p in fr]
-    arena, descs = ragged.pack_images(planes, [2] * len(planes), [1024] * len(planes),
-                                      [16] * len(planes))
+@pytest.fixture(scope="module")
+def c2_planes():
+    with ThreadPoolExecutor(WORKERS) as ex:
+        return [p for fr in ex.map(_frame, range(64)) for p in fr]
+
+
+@pytest.mark.parametrize("n,kind,q", [(32, 2, 16), (16, 1, 64)])
+def test_c2_full_size_sampled_tus(c2_planes, n, kind, q):
+    # 64 residual frames, every coefficient quantised, implicit split at the
+    # 2160 / 1080 borders: the TU-list launch the benchmark times (tuned
+    # per-bucket sequence)
+    planes = c2_planes
+    arena, descs = ragged.pack_images(planes, [kind] * len(planes), [n * n] * len(planes),
+                                      [q] * len(planes))
     tus = ragged.tu_table([synth.quadtree_tus_fast(p.shape[0], p.shape[1], synth.rng_for(0),
-                                                   p_split=0.0, ctu=32) for p in planes])
+                                                   p_split=0.0, ctu=n) for p in planes])
     plan = adct.BatchPlan(descs, tus, torch.int16)
     src = torch.from_numpy(arena).to(DEV)
     dst = torch.zeros_like(src)
@@ -96,14 +129,14 @@ def test_c2_full_size_sampled_tus():
     dst_h, kept_h = dst.cpu().numpy(), kept.cpu().numpy()
     rng = synth.rng_for(7)
     for t in rng.choice(len(tus), size=300, replace=False):
-        i, x0, y0, n = (int(tus[t][f]) for f in ("image", "x", "y", "n"))
-        want = P.compress(planes[i][y0:y0 + n, x0:x0 + n], 2, n, n * n, 16)
+        i, x0, y0, nn = (int(tus[t][f]) for f in ("image", "x", "y", "n"))
+        want = P.compress(planes[i][y0:y0 + nn, x0:x0 + nn], kind, nn, nn * nn, q)
         o = int(plan.tu_kept_offset[t])
-        assert np.array_equal(kept_h[o:o + n * n], want["kept"].reshape(-1)), t
+        assert np.array_equal(kept_h[o:o + nn * nn], want["kept"].reshape(-1)), t
         d = descs[i]
         p = int(d["pitch"])
         base = int(d["dst_offset"]) + y0 * p + x0
-        rows = np.stack([dst_h[base + yy * p: base + yy * p + n] for yy in range(n)])
+        rows = np.stack([dst_h[base + yy * p: base + yy * p + nn] for yy in range(nn)])
         assert np.array_equal(rows, want["recon"]), t
     for i in (0, 1, 2, len(planes) - 1):
         rec = ragged.unpack_image(dst_h, descs[i]).astype(np.int64)
