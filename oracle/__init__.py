@@ -11,15 +11,21 @@ Modules:
                3, 3.1, 6.1), exact inverses, scale factors, zig-zag order
   pipeline  -- tile transform, retention, quantisation, inverse, PSNR
                (sections 3.1, 5.1)
-  metrics   -- deviation from diagonality, total error energy, coding gain,
-               addition counts (sections 3.1, 4)
+  metrics   -- deviation from diagonality, total error energy, coding gain
+               (the AR(1) closed form and the 2D form from measured
+               variances), addition counts (sections 3.1, 4)
 
 Parity status: every function is pinned by the tests under ``tests/``
 against values the paper prints, closed forms or brute force, except
   * the fixed-point quantiser (the paper defines none): parity unpinned
     against the paper, pinned only against the float64 uniform quantiser it
     approximates;
-  * the coding gain of the non-orthogonal transforms under the two readings
-    of g_k: parity unpinned beyond the DCT/KLT values the paper prints.
+  * the coding gain of the non-orthogonal transforms: the columns reading of
+    g_k is pinned by the paper's description of its coding-gain figure (the
+    figure itself is missing), the rows reading only by the DCT/KLT values
+    the paper prints;
+  * the empirical 2D coding gain: pinned against the AR(1) model's
+    population moments (exactly twice the 1D gain) and, statistically, on a
+    large synthetic field; the paper defines only the model's closed form.
 """
 from . import matrices, metrics, pipeline  # noqa: F401

@@ -43,6 +43,7 @@ import numpy as np
 
 from .matrices import (diag_ttt, scale_vector, scaled_inverse, transform_matrix,
                        zigzag, near_orthogonal)
+from .metrics import coding_gain_2d, variance_from_sums
 
 QUANT_SHIFT = 24          # fixed-point bits of the forward quantiser multiplier
 QUANT_FRAC = 1            # fractional bits carried by the dequantised coefficient
@@ -230,3 +231,44 @@ def compress(img: np.ndarray, kind: int, n: int, r: int, qstep: int = 0) -> dict
     e = sse(img, recon)
     return dict(kept=kept, scaled=scaled, recon=recon, sse=e,
                 psnr=psnr(e, img.size))
+
+
+def coefficient_moments(img: np.ndarray, kind: int, n: int) -> dict:
+    """Per-image sums behind the empirical coding gain: over the tiles of
+    ``img``, the sum and the sum of squares of every integer coefficient
+    b[v][u] of B = T A T^T (``s1``, ``s2``: Python-int (N, N) object arrays),
+    and over the pixels a of A (level-shifted for 8-bit input) their sum and
+    sum of squares (``a1``, ``a2``); ``tiles`` and ``pixels`` count them.
+    Sections 4.1 and 5.1."""
+    b = forward2d(img, kind, n).reshape(-1, n, n)
+    a = level_shift(img)
+    s1 = np.empty((n, n), dtype=object)
+    s2 = np.empty((n, n), dtype=object)
+    for v in range(n):
+        for u in range(n):
+            col = b[:, v, u].astype(object)
+            s1[v, u] = int(sum(col))
+            s2[v, u] = int(sum(x * x for x in col))
+    av = a.reshape(-1).astype(object)
+    return dict(tiles=b.shape[0], s1=s1, s2=s2, pixels=a.size, a1=int(sum(av)),
+                a2=int(sum(x * x for x in av)))
+
+
+def coefficient_variances(mom: dict, kind: int, n: int):
+    """(var_c, var_x): the variance over the tiles of every scaled coefficient
+    c_vu = s_v s_u b_vu, and the variance of the pixels, from the sums of
+    ``coefficient_moments``.  Section 3.1 (the scale) and section 4.1."""
+    s = scale_vector(kind, n)
+    var_b = np.array([[variance_from_sums(mom["tiles"], mom["s1"][v, u], mom["s2"][v, u])
+                       for u in range(n)] for v in range(n)])
+    var_x = variance_from_sums(mom["pixels"], mom["a1"], mom["a2"])
+    return np.outer(s * s, s * s) * var_b, var_x
+
+
+def empirical_coding_gain(img: np.ndarray, kind: int, n: int, basis: str = "cols") -> float:
+    """2D unified coding gain (dB) of C = S' T measured on one image: the
+    coefficient and pixel variances over its tiles in place of the AR(1)
+    model's.  Section 4.1, extended to the separable 2D transform of
+    section 5.1."""
+    var_c, var_x = coefficient_variances(coefficient_moments(img, kind, n), kind, n)
+    return coding_gain_2d(near_orthogonal(kind, n), var_c, var_x, basis)
