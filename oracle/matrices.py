@@ -39,10 +39,16 @@ import math
 
 import numpy as np
 
-# transform ids used throughout: 1 = sign-based T~ (eq. 4), 2 = round-based T^ (eq. 5)
+# transform ids used throughout: 1 = sign-based T~ (eq. 4), 2 = round-based T^ (eq. 5);
+# 8-point comparison transforms of section 4: 3 = WHT (sequency order),
+# 4 = SDCT (sign of the DCT matrix), 5 = HT (Sylvester's natural order)
 SIGN = 1
 ROUND = 2
+WHT = 3
+SDCT = 4
+HT = 5
 KINDS = (SIGN, ROUND)
+COMPARISON_KINDS = (WHT, SDCT, HT)
 SIZES = (8, 16, 32)
 
 
@@ -253,7 +259,17 @@ def transform_matrix(kind: int, n: int) -> np.ndarray:
 
     N = 8: eq. 4 (kind 1) or eq. 5 (kind 2).  N > 8: the recursion of
     section 6.1, T_N = M_per_N diag(T_{N/2}, T_{N/2}) M_add_N.
+    The comparison transforms of section 4 (kinds 3, 4, 5) are 8-point
+    matrices: the Hadamard matrix in sequency order (WHT) or natural order
+    (HT) and the signed DCT.
     """
+    if kind in COMPARISON_KINDS:
+        if n != 8:
+            raise ValueError("the comparison transforms are 8-point transforms")
+        t = (sdct_matrix(8) if kind == SDCT else
+             hadamard_matrix(8, "sequency" if kind == WHT else "natural"))
+        t.setflags(write=False)
+        return t
     if kind not in KINDS:
         raise ValueError(f"unknown transform kind {kind}")
     if n == 8:

@@ -270,3 +270,45 @@ def test_zigzag_prefix_keeps_a_prefix_of_every_column(n):
         for u in range(n):
             kept = [v for v in range(n) if pos[(v, u)] < r]
             assert kept == list(range(len(kept)))
+
+
+# --------------------------------------- comparison transforms of section 4
+def test_comparison_kinds_are_the_section4_matrices(paper_values):
+    """transform_matrix serves the 8-point comparison transforms: their
+    orthonormalised forms reproduce the total error energies of Table 1
+    (WHT 5.05, HT 47.61, SDCT 3.32) and SDCT's deviation from diagonality."""
+    from oracle import metrics as Q
+    c = M.dct2_matrix(8)
+    want = {M.WHT: 5.05, M.HT: 47.61, M.SDCT: paper_values["total_error_energy"]["sdct_8"]}
+    for kind in M.COMPARISON_KINDS:
+        assert round(Q.total_error_energy(c, M.near_orthogonal(kind, 8)), 2) == want[kind]
+        t = M.transform_matrix(kind, 8)
+        # every AC row sums to zero (the level shift folds into the DC term)
+        assert np.all(t[1:].sum(axis=1) == 0) and np.all(t[0] == 1)
+        # the exact inverse is integral after scaling by 8
+        u = M.scaled_inverse(kind, 8)
+        assert np.array_equal(t @ u, 8 * np.eye(8, dtype=np.int64))
+    t = M.transform_matrix(M.SDCT, 8)
+    assert np.array_equal(t, np.sign(M.dct2_matrix(8)).astype(np.int64))
+    assert round(Q.deviation_from_diagonality(t @ t.T), 2) == \
+        paper_values["deviation_from_diagonality"]["sdct_8"]
+    for kind in (M.WHT, M.HT):
+        t = M.transform_matrix(kind, 8)
+        assert np.array_equal(t @ t.T, 8 * np.eye(8, dtype=np.int64))
+    with pytest.raises(ValueError):
+        M.transform_matrix(M.WHT, 16)
+
+
+def test_comparison_kinds_in_the_pipeline():
+    """The pipeline's special cases hold for the comparison transforms:
+    r = 64 reconstructs exactly, r = 1 gives the rounded block mean."""
+    from oracle import pipeline as P
+    rng = np.random.default_rng(5)
+    img = rng.integers(0, 256, size=(16, 24), dtype=np.uint8)
+    for kind in M.COMPARISON_KINDS:
+        assert np.array_equal(P.compress(img, kind, 8, 64)["recon"], img)
+        rec = P.compress(img, kind, 8, 1)["recon"]
+        tiles = img.reshape(2, 8, 3, 8).astype(np.int64).sum(axis=(1, 3))
+        mean = np.sign(tiles) * ((2 * np.abs(tiles - 0) + 64) // 128)   # round(sum / 64)
+        want = np.repeat(np.repeat(mean, 8, axis=0), 8, axis=1)
+        assert np.array_equal(rec.astype(np.int64), want)
