@@ -7,7 +7,10 @@ T in {T1, T2} x r in {1, 6, 10, 16, 28, 45, 64} with N = 8: 14 fused launches,
 each doing level shift, forward 2D transform, zig-zag retention, the
 orthogonalising scale, the inverse transform, rounding/clipping and the
 per-image error energy, and writing the retained int32 coefficients, the
-float32 scaled coefficients, the reconstruction and the error energies.
+float32 scaled coefficients, the reconstruction and the error energies, each
+followed by the float32 PSNR of every image; and, once per transform (they do
+not depend on r), the coefficient moments of every image and its float32
+measured coding gain.
 
 Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
 the build targets one GPU.
@@ -206,21 +209,27 @@ def c1_images(pool, b, h, w):
 
 # ------------------------------------------------------------------ CPU leg
 def _oracle_task(args):
-    """One oracle pass over one image; returns (seconds in the oracle, pixels)."""
+    """One oracle task over one image: a fused pass (r > 0) or the measured
+    coding gain (r = 0, once per transform); returns (seconds in the oracle,
+    pixels of the sweep the task stands for)."""
     img, kind, r = args
     from oracle import pipeline as P
     t0 = time.perf_counter()
-    P.compress(img, kind, N, r)
-    return time.perf_counter() - t0, img.size
+    if r:
+        P.compress(img, kind, N, r)
+        return time.perf_counter() - t0, img.size
+    P.empirical_coding_gain(img, kind, N, "cols")
+    return time.perf_counter() - t0, 0
 
 
 def cpu_baseline(pool, sample):
     """The oracle as it stands, timed on the host's cores over a bounded
-    sample: the full 14-point T x r sweep of ``sample`` (images drawn before
-    the timed region), one (image, T, r) pass per task.  ``value`` is pixels
-    over the wall time of the oracle passes; the summed time inside the oracle
-    is reported beside it."""
-    tasks = [(img, k, r) for img in sample for k in KINDS for r in SWEEP_R]
+    sample of the step: for every image of ``sample`` (drawn before the timed
+    region) the full 14-point T x r sweep (compress with PSNR) and the measured
+    coding gain of both transforms, one task per (image, T, r) pass or (image,
+    T) gain.  ``value`` is pixels over the wall time of the oracle tasks; the
+    summed time inside the oracle is reported beside it."""
+    tasks = [(img, k, r) for img in sample for k in KINDS for r in (0,) + SWEEP_R]
     t0 = time.perf_counter()
     res = pool.map(_oracle_task, tasks)
     wall = time.perf_counter() - t0
@@ -229,9 +238,10 @@ def cpu_baseline(pool, sample):
     h, w = sample[0].shape
     return {"value": px / wall / 1e9, "unit": "Gpixel/s", "cores": pool.workers,
             "kind": "oracle",
-            "sample": f"{len(sample)} images of {h}x{w} from the same batch, full T x r sweep "
-                      f"({len(tasks)} passes, {px / 1e9:.2f} Gpx): {cpu_s:.1f} s inside the "
-                      f"oracle over {pool.workers} {pool.kind}, {wall:.2f} s wall",
+            "sample": f"{len(sample)} images of {h}x{w} from the same batch, the whole step: "
+                      f"T x r sweep ({len(sample) * len(KINDS) * len(SWEEP_R)} passes, "
+                      f"{px / 1e9:.2f} Gpx) and the coding gain of both T: {cpu_s:.1f} s "
+                      f"inside the oracle over {pool.workers} {pool.kind}, {wall:.2f} s wall",
             "oracle_seconds": round(cpu_s, 2), "wall_seconds": round(wall, 3),
             "workers": pool.kind, "host_cpus": os.cpu_count(),
             "cpu_model": cpu_model()}
@@ -379,6 +389,9 @@ def gpu_c1(args, imgs, cpu):
     scaled_buf = torch.empty(tiles * rmax, dtype=torch.float32, device=dev)
     recon = torch.empty_like(x)
     sse = torch.zeros(b, dtype=torch.uint64, device=dev)
+    psnr = torch.zeros((len(KINDS), len(SWEEP_R), b), dtype=torch.float32, device=dev)
+    mom = torch.zeros((len(KINDS), b, 3 * N * N + 4), dtype=torch.uint64, device=dev)
+    cg = torch.zeros((len(KINDS), b), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log("inputs resident on the GPU")
 
@@ -396,15 +409,28 @@ def gpu_c1(args, imgs, cpu):
         return (kept_buf[: tiles * r].view(b, h // N, w // N, r),
                 scaled_buf[: tiles * r].view(b, h // N, w // N, r))
 
-    def one_step(events=None):
-        for i, (k, r) in enumerate(combos):
-            kv, sv = views(r)
-            if events is not None:
-                events[i][0].record()
-            adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse,
-                          engine=args.engine)
-            if events is not None:
-                events[i][1].record()
+    def one_step(events=None, mom_events=None):
+        # per transform: the coefficient moments and the measured coding gain
+        # (they do not depend on r), then the fused pass and PSNR of every r
+        for ki, k in enumerate(KINDS):
+            mom[ki].zero_()
+            if mom_events is not None:
+                mom_events[ki][0].record()
+            adct.moments(x, k, N, out=mom[ki])
+            if mom_events is not None:
+                mom_events[ki][1].record()
+            adct.coding_gain(mom[ki], k, N, "cols", out=cg[ki])
+            for ri, r in enumerate(SWEEP_R):
+                i = ki * len(SWEEP_R) + ri
+                kv, sv = views(r)
+                sse.zero_()
+                if events is not None:
+                    events[i][0].record()
+                adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse,
+                              engine=args.engine)
+                if events is not None:
+                    events[i][1].record()
+                adct.psnr(sse, h * w, out=psnr[ki, ri])
 
     for _ in range(args.warmup):
         one_step()
@@ -414,12 +440,14 @@ def gpu_c1(args, imgs, cpu):
     # events recorded on the current stream, the one the launches go to
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
            for _ in combos] for _ in range(args.steps)]
+    mev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in KINDS] for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for s in range(args.steps):
-        one_step(ev[s])
+        one_step(ev[s], mev[s])
     stop.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
@@ -439,6 +467,10 @@ def gpu_c1(args, imgs, cpu):
         tot_ms += ms
         kernels.append({"T": k, "r": r, "ms": round(ms, 4), "GBps": round(by / ms / 1e6, 1)})
     achieved = tot_bytes / tot_ms / 1e6   # GB/s, averaged over the 14 launches
+    mom_ms = sum(mev[s][ki][0].elapsed_time(mev[s][ki][1])
+                 for s in range(args.steps) for ki in range(len(KINDS))) / (args.steps * len(KINDS))
+    moments_kernel = {"ms": round(mom_ms, 4), "GBps": round(b * h * w / mom_ms / 1e6, 1),
+                      "bytes": "pixels read once, 8 B per coefficient sum per workgroup"}
     px_per_step = b * h * w * len(combos)
     value = px_per_step * args.steps / (total_ms / 1e3) / 1e9
 
@@ -453,12 +485,21 @@ def gpu_c1(args, imgs, cpu):
         adct.compress(x, k, N, r, kept=kv, scaled=sv, recon=recon, sse=sse, engine=args.engine)
         torch.cuda.synchronize()
         picks = sorted({0, b // 2, b - 1})
+        psnr_h = psnr.cpu().numpy().astype(np.float64)
+        cg_h = cg.cpu().numpy().astype(np.float64)
+
+        def near(got, want):
+            return got == want or abs(got - want) <= 1e-5 * max(abs(want), 1.0)
 
         def one(i):
             want = P.compress(imgs[i], k, N, r)
             bad = int(not np.array_equal(kv[i].cpu().numpy(), want["kept"]))
             bad += int(not np.array_equal(recon[i].cpu().numpy(), want["recon"]))
             bad += int(int(sse[i].item()) != want["sse"])
+            # PSNR and coding gain of the timed steps
+            bad += int(not near(psnr_h[KINDS.index(k), SWEEP_R.index(r), i], want["psnr"]))
+            for ki, kk in enumerate(KINDS):
+                bad += int(not near(cg_h[ki, i], P.empirical_coding_gain(imgs[i], kk, N, "cols")))
             got_s = sv[i].cpu().numpy().astype(np.float64)
             nz = want["scaled"] != 0
             bad += int(not np.all(got_s[~nz] == 0))
@@ -469,7 +510,8 @@ def gpu_c1(args, imgs, cpu):
         with ThreadPoolExecutor(len(picks)) as ex:
             bad = sum(ex.map(one, picks))
         check = "ok" if bad == 0 else f"{bad} mismatches"
-        log(f"sampled parity vs oracle (T2, r=10, images {picks}): {check}")
+        log(f"sampled parity vs oracle (T2, r=10 outputs and PSNR, coding gain of T1 and T2; "
+            f"images {picks}): {check}")
 
     traffic = measured_traffic() if args.engine == "butterfly" else None
     kernel = ("compress8 (fused 8x8 kernel; 14 instantiations, one per (T, r))"
@@ -491,7 +533,9 @@ def gpu_c1(args, imgs, cpu):
         "config": {"workload": f"plain method at scale: {b} x {h}x{w} uint8 AR(1) images, N=8, "
                                "T1+T2 x r in {1,6,10,16,28,45,64}, fused fwd+retain+scale+inv+SSE",
                    "images": b, "height": h, "width": w, "n": N, "r_sweep": list(SWEEP_R),
-                   "outputs": "kept int32 + scaled float32 + recon uint8 + sse",
+                   "outputs": "kept int32 + scaled float32 + recon uint8 + sse + float32 "
+                              "PSNR per (T, r, image); coefficient moments + float32 measured "
+                              "coding gain per (T, image)",
                    "engine": args.engine},
         "blocks_per_s": round(tiles * len(combos) * args.steps / (total_ms / 1e3), 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -499,6 +543,9 @@ def gpu_c1(args, imgs, cpu):
                      "traffic": traffic,
                      "kernel": kernel},
         "kernels": kernels,
+        "moments_kernel": moments_kernel,
+        "coding_gain_db": {f"T{k}": round(float(cg[ki].double().mean()), 4)
+                           for ki, k in enumerate(KINDS)},
         "parity_sample": check,
         "cpu_baseline": cpu,
     }
@@ -876,7 +923,9 @@ def gpu_c3(args, d):
         from concurrent.futures import ThreadPoolExecutor
 
         from oracle import pipeline as P
-        plan.run(src, dst, kept, None, sse, psnr, mode="graph")
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):   # graph capture needs a non-null stream
+            plan.run(src, dst, kept, None, sse, psnr, mode="graph")
         torch.cuda.synchronize()
         dst_h = dst.cpu().numpy()
         kept_h = kept.cpu().numpy()

@@ -17,6 +17,12 @@
  *              section 6.1.
  *              ADCT_T2: the round-based approximation T^_N (eq. 5 and
  *              section 6.1).
+ *              ADCT_WHT, ADCT_SDCT, ADCT_HT: three of the 8-point transforms
+ *              section 4 compares against (n = 8 only; ADCT_E_ARG otherwise).
+ *              All three have add-only fast algorithms (24 additions, Table
+ *              2) and exact integer inverses N T^-1, so every device call
+ *              below computes them with the same kernels (the ragged-batch
+ *              and serving calls take ADCT_T1 and ADCT_T2 only).
  *   n          block length N in {8, 16, 32}.
  *   dtype      ADCT_U8: 8-bit grey levels, shifted by -128 before the
  *              transform and reconstructed as round(.) + 128 clipped to
@@ -56,6 +62,10 @@ extern "C" {
 
 #define ADCT_T1 1
 #define ADCT_T2 2
+/* Comparison transforms of section 4 (Tables 1 and 2), n = 8 only: */
+#define ADCT_WHT 3   /* Walsh-Hadamard, rows in sequency order  */
+#define ADCT_SDCT 4  /* signed DCT, sign(C8)                    */
+#define ADCT_HT 5    /* Hadamard, Sylvester's natural row order */
 
 #define ADCT_U8 0
 #define ADCT_I16 1
@@ -164,6 +174,67 @@ ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int bat
                                 int width, int64_t pitch, int64_t image_stride, int32_t* d_kept,
                                 float* d_scaled, void* d_recon, uint64_t* d_sse,
                                 adct_stream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Quality measures: PSNR (section 5.1) and the unified coding gain
+ * (section 4.1), in float32.
+ * ---------------------------------------------------------------------- */
+
+/* g_k of the coding gain: the rows of C^-1 (as section 4.1 words it) or its
+ * columns (the synthesis basis).  Both agree for orthogonal transforms. */
+#define ADCT_BASIS_ROWS 0
+#define ADCT_BASIS_COLS 1
+
+/* uint64 words of one moment record of block length n. */
+#define ADCT_MOMENT_WORDS(n) (3 * (n) * (n) + 4)
+
+/* PSNR of section 5.1 from error energies: d_psnr[i] = 10 log10(255^2 *
+ * pixels / d_sse[i]) in float32, +inf where d_sse[i] = 0 (device arrays of
+ * count entries; pixels >= 1 is the pixel count of every image).  count = 0
+ * is a no-op. */
+ADCT_API int adct_psnr(int count, int64_t pixels, const uint64_t* d_sse, float* d_psnr,
+                       adct_stream_t stream);
+
+/* Moments of the coefficients b[v][u] of B = T A T^T over the tiles of each
+ * image (section 5.1), and of its pixels a (8-bit input shifted by -128),
+ * ADDED to the record of that image (the caller zeroes the records first;
+ * records of several calls may be accumulated).  d_moments holds batch
+ * records of ADCT_MOMENT_WORDS(n) uint64 words, 8-byte aligned device memory:
+ *   [p]            sum over tiles of b_p, as two's complement int64,
+ *                  p = v * n + u;
+ *   [n*n + p]      sum over tiles of (b_p^2 mod 2^32);
+ *   [2*n*n + p]    sum over tiles of floor(b_p^2 / 2^32), so that the sum of
+ *                  b_p^2 is word[2n^2 + p] * 2^32 + word[n^2 + p];
+ *   [3*n*n]        tiles;   [3*n*n + 1] pixels;
+ *   [3*n*n + 2]    sum of a (two's complement int64);  [3*n*n + 3] sum of a^2.
+ * Every sum is exact for every input of up to 2^32 tiles per image.  Image
+ * set arguments as for adct_fwd2d.  Only d_moments is written. */
+ADCT_API int adct_moments(int transform, int n, const void* d_src, int dtype, int batch,
+                          int height, int width, int64_t pitch, int64_t image_stride,
+                          uint64_t* d_moments, adct_stream_t stream);
+
+/* Measured 2D coding gain (dB) of each of count moment records (as
+ * adct_moments writes them, same transform and n): the unified coding gain of
+ * section 4.1 for the separable transform C (x) C, C = S' T, with A_vu the
+ * variance of the orthonormal coefficient s_v s_u b_vu over the tiles divided
+ * by the pixel variance, and B_v B_u the squared norm of the synthesis vector
+ * g_v g_u^T (basis: ADCT_BASIS_ROWS or ADCT_BASIS_COLS):
+ *   d_cg[i] = -10 / n^2 * sum_vu log10(A_vu B_v B_u).
+ * +inf when a coefficient has zero variance, NaN when the pixels have zero
+ * variance or the record is empty.  float32 output, device arrays. */
+ADCT_API int adct_coding_gain(int transform, int n, int basis, int count,
+                              const uint64_t* d_moments, float* d_cg, adct_stream_t stream);
+
+/* Coding gain (dB) of C = S' T under the first-order Markov model of section
+ * 4.1, R_x[m][n] = rho^|m - n|, for count correlation values d_rho[i] in
+ * [0, 1) (device float32): d_cg[i] = -10 / n * sum_k log10(A_k B_k) with
+ * A_k = h_k R_x h_k^T, h_k row k of C, and B_k the squared norm of row or
+ * column k of C^-1 (basis).  d_cg_klt[i] receives the KLT's gain for the same
+ * rho, -10 / n * sum log10 lambda(R_x) = -10 (n-1)/n log10(1 - rho^2).
+ * Either output may be NULL.  float32, device arrays. */
+ADCT_API int adct_coding_gain_ar1(int transform, int n, int basis, int count,
+                                  const float* d_rho, float* d_cg, float* d_cg_klt,
+                                  adct_stream_t stream);
 
 /* ----------------------------------------------------------------------
  * Ragged batches: many images of different sizes, each partitioned into

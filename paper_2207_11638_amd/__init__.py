@@ -21,6 +21,7 @@ from ._lib import ADCT_I16, ADCT_T1, ADCT_T2, ADCT_U8, AdctError
 
 __all__ = ["ADCT_T1", "ADCT_T2", "AdctError", "get_matrix", "zigzag", "scale_vector",
            "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path",
+           "psnr", "moments", "coding_gain", "coding_gain_ar1",
            "BatchPlan", "IMAGE_DESC", "TU_DESC"]
 
 library_path = _lib.LIB_PATH
@@ -185,6 +186,76 @@ def decompress(kept, transform: int, n: int, r: int, qstep: int = 0, dtype=None,
                                            _dtype_code(out), ob, h, w, pitch, istride,
                                            _stream_handle(kept.device)))
     return out
+
+
+# ----------------------------------------------------------------- quality measures
+_BASES = {"rows": _lib.ADCT_BASIS_ROWS, "cols": _lib.ADCT_BASIS_COLS}
+
+
+def _basis_code(basis: str) -> int:
+    if basis not in _BASES:
+        raise ValueError(f"basis must be 'rows' or 'cols', got {basis!r}")
+    return _BASES[basis]
+
+
+def psnr(sse, pixels: int, out=None):
+    """float32 PSNR per image from uint64 error energies [B] (images of
+    ``pixels`` pixels each); +inf where the error energy is zero."""
+    torch = _torch()
+    _require_device(sse, out)
+    if sse.dtype != torch.uint64 or not sse.is_contiguous() or sse.dim() != 1:
+        raise ValueError("sse must be a contiguous uint64 [B] tensor")
+    if out is None:
+        out = torch.empty(sse.numel(), dtype=torch.float32, device=sse.device)
+    _lib.check(_lib.load().adct_psnr(sse.numel(), int(pixels), _ptr(sse), _ptr(out),
+                                     _stream_handle(sse.device)))
+    return out
+
+
+def moments(x, transform: int, n: int, out=None):
+    """Coefficient and pixel moments of every image: uint64 [B, 3 n^2 + 4]
+    (layout of adct_moments), accumulated into ``out`` when it is given."""
+    torch = _torch()
+    _require_device(x, out)
+    b, h, w, pitch, istride = _image_geometry(x)
+    if out is None:
+        out = torch.zeros((b, _lib.moment_words(n)), dtype=torch.uint64, device=x.device)
+    elif (out.dtype != torch.uint64 or not out.is_contiguous() or
+          tuple(out.shape) != (b, _lib.moment_words(n))):
+        raise ValueError("out must be a contiguous uint64 [B, 3 n^2 + 4] tensor")
+    _lib.check(_lib.load().adct_moments(transform, n, _ptr(x), _dtype_code(x), b, h, w, pitch,
+                                        istride, _ptr(out), _stream_handle(x.device)))
+    return out
+
+
+def coding_gain(mom, transform: int, n: int, basis: str = "cols", out=None):
+    """Measured 2D coding gain (dB, float32) of every moment record [B, 3 n^2 + 4]."""
+    torch = _torch()
+    _require_device(mom, out)
+    if (mom.dtype != torch.uint64 or not mom.is_contiguous() or mom.dim() != 2 or
+            mom.shape[1] != _lib.moment_words(n)):
+        raise ValueError("moments must be a contiguous uint64 [B, 3 n^2 + 4] tensor")
+    if out is None:
+        out = torch.empty(mom.shape[0], dtype=torch.float32, device=mom.device)
+    _lib.check(_lib.load().adct_coding_gain(transform, n, _basis_code(basis), mom.shape[0],
+                                            _ptr(mom), _ptr(out), _stream_handle(mom.device)))
+    return out
+
+
+def coding_gain_ar1(rho, transform: int, n: int, basis: str = "cols"):
+    """Coding gain (dB, float32) of C = S' T under the AR(1) model for every
+    correlation value in the float32 device tensor ``rho``; returns
+    (gain, KLT gain)."""
+    torch = _torch()
+    _require_device(rho)
+    if rho.dtype != torch.float32 or not rho.is_contiguous() or rho.dim() != 1:
+        raise ValueError("rho must be a contiguous float32 vector")
+    cg = torch.empty_like(rho)
+    klt = torch.empty_like(rho)
+    _lib.check(_lib.load().adct_coding_gain_ar1(transform, n, _basis_code(basis), rho.numel(),
+                                                _ptr(rho), _ptr(cg), _ptr(klt),
+                                                _stream_handle(rho.device)))
+    return cg, klt
 
 
 # ----------------------------------------------------------------- ragged batches

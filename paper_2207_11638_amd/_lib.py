@@ -31,6 +31,10 @@ _SIGNATURES = {
                        _vp, _vp, _vp], _i32),
     "adct_compress_mfma": ([_i32, _i32, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
                             _vp], _i32),
+    "adct_psnr": ([_i32, _i64, _vp, _vp, _vp], _i32),
+    "adct_moments": ([_i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp], _i32),
+    "adct_coding_gain": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
+    "adct_coding_gain_ar1": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp], _i32),
     "adct_batch_create": ([_vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp], _i32),
     "adct_batch_destroy": ([_vp], _i32),
     "adct_batch_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
@@ -46,6 +50,14 @@ _SIGNATURES = {
     "adct_server_clock_ms": ([_vp], C.c_double),
     "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp], _i32),
 }
+
+ADCT_BASIS_ROWS, ADCT_BASIS_COLS = 0, 1
+
+
+def moment_words(n: int) -> int:
+    """uint64 words of one moment record (ADCT_MOMENT_WORDS)."""
+    return 3 * n * n + 4
+
 
 ADCT_RUN_BATCHED, ADCT_RUN_GRAPH, ADCT_RUN_PER_IMAGE, ADCT_RUN_UNIFIED = 0, 1, 2, 3
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/adct.h"
 #include "butterflies.hpp"
 
 namespace adct {
@@ -83,6 +84,16 @@ enum class Mode : int { Compress = 0, Forward = 1, Inverse = 2, Decompress = 3 }
 // Kernel launchers (return hipError_t as int).
 int launch_n8(Mode mode, int kind, int dtype, const PassParams& p, hipStream_t stream);
 int launch_jam(Mode mode, int kind, int n, int dtype, const PassParams& p, hipStream_t stream);
+// Quality measures (quality.hip): coefficient and pixel moments per image,
+// the measured and the AR(1) coding gain, PSNR from error energies.
+int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
+                   unsigned long long* mom, hipStream_t s);
+int launch_coding_gain(int kind, int n, int basis, const unsigned long long* mom, int count,
+                       float* cg, hipStream_t s);
+int launch_coding_gain_ar1(int kind, int n, int basis, const float* rho, int count, float* cg,
+                           float* cg_klt, hipStream_t s);
+int launch_psnr(const unsigned long long* sse, int count, int64_t pixels, float* psnr,
+                hipStream_t s);
 // Fused 8x8 compress (uint8, zonal) on the int8 matrix cores; t = T[v][i] and
 // u = (8 T^-1)[i][v], row-major.
 int launch_n8_mfma(int kind, const PassParams& p, const int8_t* t, const int8_t* u,

@@ -32,7 +32,9 @@ int ok() {
   return ADCT_OK;
 }
 
-bool valid_kind(int t) { return t == ADCT_T1 || t == ADCT_T2; }
+bool valid_kind(int t) { return t >= ADCT_T1 && t <= ADCT_HT; }
+// the comparison transforms of section 4 are 8-point transforms
+bool valid_kind_n(int t, int n) { return t == ADCT_T1 || t == ADCT_T2 || n == 8; }
 bool valid_n(int n) { return n == 8 || n == 16 || n == 32; }
 
 // Apply the forward (inverse = false) or inverse butterfly of (kind, n) to a
@@ -45,7 +47,13 @@ void apply_1d(int kind, int n, bool inverse, int* v) {
     if (inverse) invN<K, NN>(tmp); else fwdN<K, NN>(tmp); \
     for (int i = 0; i < NN; ++i) v[i] = tmp[i];       \
   } while (0)
-  if (kind == KIND_SIGN) {
+  if (kind == KIND_WHT) {
+    ADCT_APPLY(KIND_WHT, 8);
+  } else if (kind == KIND_SDCT) {
+    ADCT_APPLY(KIND_SDCT, 8);
+  } else if (kind == KIND_HT) {
+    ADCT_APPLY(KIND_HT, 8);
+  } else if (kind == KIND_SIGN) {
     if (n == 8) ADCT_APPLY(KIND_SIGN, 8);
     else if (n == 16) ADCT_APPLY(KIND_SIGN, 16);
     else ADCT_APPLY(KIND_SIGN, 32);
@@ -97,7 +105,13 @@ void classes_of(std::vector<int64_t>& vals, std::vector<int>& cls) {
 int build_tables(int kind, int n, int qstep, TableSet& out) {
   std::vector<int64_t> vals;
   std::vector<int> cls;
-  if (kind == KIND_SIGN) {
+  if (kind == KIND_WHT) {
+    classes_of<KIND_WHT, 8>(vals, cls);
+  } else if (kind == KIND_SDCT) {
+    classes_of<KIND_SDCT, 8>(vals, cls);
+  } else if (kind == KIND_HT) {
+    classes_of<KIND_HT, 8>(vals, cls);
+  } else if (kind == KIND_SIGN) {
     if (n == 8) classes_of<KIND_SIGN, 8>(vals, cls);
     else if (n == 16) classes_of<KIND_SIGN, 16>(vals, cls);
     else classes_of<KIND_SIGN, 32>(vals, cls);
@@ -160,6 +174,8 @@ int check_images(const char* what, int n, int dtype, const void* ptr, int batch,
 int check_common(int transform, int n) {
   if (!valid_kind(transform)) return fail(ADCT_E_ARG, "bad transform id %d", transform);
   if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d (8, 16 or 32)", n);
+  if (!valid_kind_n(transform, n))
+    return fail(ADCT_E_ARG, "transform %d is an 8-point transform (n=%d)", transform, n);
   return ADCT_OK;
 }
 
@@ -374,6 +390,78 @@ ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int bat
     u8m[i] = static_cast<int8_t>(inv[i] / 2);
   }
   const int e = launch_n8_mfma(transform, p, t8m, u8m, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+ADCT_API int adct_psnr(int count, int64_t pixels, const uint64_t* d_sse, float* d_psnr,
+                       adct_stream_t stream) {
+  if (count < 0) return fail(ADCT_E_ARG, "psnr: negative count");
+  if (count == 0) return ok();
+  if (pixels < 1) return fail(ADCT_E_ARG, "psnr: pixels must be positive");
+  if (d_sse == nullptr || d_psnr == nullptr) return fail(ADCT_E_ARG, "psnr: null pointer");
+  if ((reinterpret_cast<uintptr_t>(d_sse) % 8) || (reinterpret_cast<uintptr_t>(d_psnr) % 4))
+    return fail(ADCT_E_ALIGN, "psnr: misaligned buffer");
+  const int e = launch_psnr(reinterpret_cast<const unsigned long long*>(d_sse), count, pixels,
+                            d_psnr, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+ADCT_API int adct_moments(int transform, int n, const void* d_src, int dtype, int batch,
+                          int height, int width, int64_t pitch, int64_t image_stride,
+                          uint64_t* d_moments, adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  Geom g{};
+  if (int s = check_images("moments", n, dtype, d_src, batch, height, width, pitch, image_stride, g))
+    return s;
+  if (g.batch == 0 || g.tiles_x == 0 || g.tiles_y == 0) return ok();
+  if (d_src == nullptr || d_moments == nullptr) return fail(ADCT_E_ARG, "moments: null pointer");
+  if (reinterpret_cast<uintptr_t>(d_moments) % 8) return fail(ADCT_E_ALIGN, "moments: misaligned records");
+  if (static_cast<int64_t>(g.tiles_x) * g.tiles_y >= (int64_t(1) << 32))
+    return fail(ADCT_E_SHAPE, "moments: more than 2^32 tiles per image");
+  const int e = launch_moments(transform, n, dtype, d_src, g,
+                               reinterpret_cast<unsigned long long*>(d_moments),
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+ADCT_API int adct_coding_gain(int transform, int n, int basis, int count,
+                              const uint64_t* d_moments, float* d_cg, adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
+    return fail(ADCT_E_ARG, "coding_gain: bad basis %d", basis);
+  if (count < 0) return fail(ADCT_E_ARG, "coding_gain: negative count");
+  if (count == 0) return ok();
+  if (d_moments == nullptr || d_cg == nullptr) return fail(ADCT_E_ARG, "coding_gain: null pointer");
+  if ((reinterpret_cast<uintptr_t>(d_moments) % 8) || (reinterpret_cast<uintptr_t>(d_cg) % 4))
+    return fail(ADCT_E_ALIGN, "coding_gain: misaligned buffer");
+  const int e = launch_coding_gain(transform, n, basis,
+                                   reinterpret_cast<const unsigned long long*>(d_moments), count,
+                                   d_cg, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+ADCT_API int adct_coding_gain_ar1(int transform, int n, int basis, int count,
+                                  const float* d_rho, float* d_cg, float* d_cg_klt,
+                                  adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
+    return fail(ADCT_E_ARG, "coding_gain_ar1: bad basis %d", basis);
+  if (count < 0) return fail(ADCT_E_ARG, "coding_gain_ar1: negative count");
+  if (count == 0 || (d_cg == nullptr && d_cg_klt == nullptr)) return ok();
+  if (d_rho == nullptr) return fail(ADCT_E_ARG, "coding_gain_ar1: null rho");
+  if ((reinterpret_cast<uintptr_t>(d_rho) % 4) || (reinterpret_cast<uintptr_t>(d_cg) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_cg_klt) % 4))
+    return fail(ADCT_E_ALIGN, "coding_gain_ar1: misaligned buffer");
+  const int e = launch_coding_gain_ar1(transform, n, basis, d_rho, count, d_cg, d_cg_klt,
+                                       static_cast<hipStream_t>(stream));
   if (e != hipSuccess)
     return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();

@@ -29,11 +29,108 @@
 
 namespace adct {
 
-enum : int { KIND_SIGN = 1, KIND_ROUND = 2 };
+// Transform ids: the two proposed approximations (section 3) and three of the
+// 8-point comparison transforms of section 4 (Tables 1 and 2).
+enum : int { KIND_SIGN = 1, KIND_ROUND = 2, KIND_WHT = 3, KIND_SDCT = 4, KIND_HT = 5 };
+
+// ------------------------------------------- comparison transforms (N = 8)
+// Walsh-Hadamard: three radix-2 stages (24 additions) give the Hadamard
+// transform in Sylvester's natural row order (HT); the WHT lists the same
+// rows by sequency (number of sign changes).  H H^T = 8 I, so the integer
+// inverse chain 16 H^-1 is 2 H^T.
+template <bool SEQUENCY>
+ADCT_HD void hadamard8(int (&x)[8]) {
+  int y[8] = {};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    y[i] = x[i] + x[i + 4];
+    y[i + 4] = x[i] - x[i + 4];
+  }
+  int z[8] = {};
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      z[4 * h + i] = y[4 * h + i] + y[4 * h + i + 2];
+      z[4 * h + i + 2] = y[4 * h + i] - y[4 * h + i + 2];
+    }
+  int n[8] = {};   // natural order: n[i] = sum_j (-1)^popcount(i & j) x[j]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    n[2 * q] = z[2 * q] + z[2 * q + 1];
+    n[2 * q + 1] = z[2 * q] - z[2 * q + 1];
+  }
+  if constexpr (SEQUENCY) {
+    // natural row of sequency k: 0, 4, 6, 2, 3, 7, 5, 1
+    x[0] = n[0]; x[1] = n[4]; x[2] = n[6]; x[3] = n[2];
+    x[4] = n[3]; x[5] = n[7]; x[6] = n[5]; x[7] = n[1];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = n[i];
+  }
+}
+
+template <bool SEQUENCY>
+ADCT_HD void hadamard8_inv(int (&X)[8]) {
+  int n[8] = {};
+  if constexpr (SEQUENCY) {
+    n[0] = X[0]; n[4] = X[1]; n[6] = X[2]; n[2] = X[3];
+    n[3] = X[4]; n[7] = X[5]; n[5] = X[6]; n[1] = X[7];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) n[i] = X[i];
+  }
+  hadamard8<false>(n);   // H_natural is symmetric
+#pragma unroll
+  for (int i = 0; i < 8; ++i) X[i] = 2 * n[i];
+}
+
+// Signed DCT, sign(C8): the pre-additions B8 split x into sums s and
+// differences d; the even rows are a 4-point Hadamard of s, the odd rows a
+// 4-point chain on d (24 additions in all, Table 2).
+ADCT_HD void sdct8(int (&x)[8]) {
+  const int s0 = x[0] + x[7], s1 = x[1] + x[6], s2 = x[2] + x[5], s3 = x[3] + x[4];
+  const int d0 = x[0] - x[7], d1 = x[1] - x[6], d2 = x[2] - x[5], d3 = x[3] - x[4];
+  const int e0 = s0 + s3, e1 = s1 + s2, e2 = s0 - s3, e3 = s1 - s2;
+  const int a = d0 - d1, b = d2 + d3, c = d2 - d3, p = d0 + d1;
+  x[0] = e0 + e1;
+  x[2] = e2 + e3;
+  x[4] = e0 - e1;
+  x[6] = e2 - e3;
+  x[1] = p + b;
+  x[3] = a - b;
+  x[5] = a + b;
+  x[7] = a + c;
+}
+
+// 16 sign(C8)^-1 = B8^T diag(2 E^T, 8 O^-1) with E the even 4-point Hadamard
+// (E E^T = 4 I) and 8 O^-1 = 4 [[1,1,0,0],[1,0,-1,0],[0,-1,0,1],[0,0,1,-1]]
+// for the odd rows.
+ADCT_HD void sdct8_inv(int (&X)[8]) {
+  const int f0 = X[0] + X[4], f1 = X[0] - X[4], f2 = X[2] + X[6], f3 = X[2] - X[6];
+  const int s0 = 2 * (f0 + f2), s1 = 2 * (f1 + f3), s2 = 2 * (f1 - f3), s3 = 2 * (f0 - f2);
+  const int d0 = 4 * (X[1] + X[3]), d1 = 4 * (X[1] - X[5]);
+  const int d2 = 4 * (X[7] - X[3]), d3 = 4 * (X[5] - X[7]);
+  X[0] = s0 + d0;
+  X[1] = s1 + d1;
+  X[2] = s2 + d2;
+  X[3] = s3 + d3;
+  X[4] = s3 - d3;
+  X[5] = s2 - d2;
+  X[6] = s1 - d1;
+  X[7] = s0 - d0;
+}
 
 // ------------------------------------------------------------ 8-point forward
 template <int KIND>
 ADCT_HD void fwd8(int (&x)[8]) {
+  if constexpr (KIND == KIND_WHT || KIND == KIND_HT) {
+    hadamard8<KIND == KIND_WHT>(x);
+    return;
+  } else if constexpr (KIND == KIND_SDCT) {
+    sdct8(x);
+    return;
+  }
   // B8: pre-additions
   const int y0 = x[0] + x[7], y1 = x[1] + x[6], y2 = x[2] + x[5], y3 = x[3] + x[4];
   const int y4 = x[3] - x[4], y5 = x[2] - x[5], y6 = x[1] - x[6], y7 = x[0] - x[7];
@@ -76,6 +173,13 @@ ADCT_HD void fwd8(int (&x)[8]) {
 // ------------------------------------------------ 8-point inverse (K8 = 16 T^-1)
 template <int KIND>
 ADCT_HD void inv8(int (&X)[8]) {
+  if constexpr (KIND == KIND_WHT || KIND == KIND_HT) {
+    hadamard8_inv<KIND == KIND_WHT>(X);
+    return;
+  } else if constexpr (KIND == KIND_SDCT) {
+    sdct8_inv(X);
+    return;
+  }
   // P8^T then M1^T
   const int v0 = X[0], v1 = X[2], v2 = X[4], v3 = X[6];
   const int v4 = X[1], v5 = X[5], v6 = X[3], v7 = X[7];

@@ -178,6 +178,15 @@ hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
 }  // namespace
 
 int launch_n8(Mode mode, int kind, int dtype, const PassParams& p, hipStream_t stream) {
+  if (kind == KIND_WHT)
+    return dtype == DT_U8 ? launch_typed<KIND_WHT, DT_U8>(mode, p, stream)
+                          : launch_typed<KIND_WHT, DT_I16>(mode, p, stream);
+  if (kind == KIND_SDCT)
+    return dtype == DT_U8 ? launch_typed<KIND_SDCT, DT_U8>(mode, p, stream)
+                          : launch_typed<KIND_SDCT, DT_I16>(mode, p, stream);
+  if (kind == KIND_HT)
+    return dtype == DT_U8 ? launch_typed<KIND_HT, DT_U8>(mode, p, stream)
+                          : launch_typed<KIND_HT, DT_I16>(mode, p, stream);
   if (kind == KIND_SIGN)
     return dtype == DT_U8 ? launch_typed<KIND_SIGN, DT_U8>(mode, p, stream)
                           : launch_typed<KIND_SIGN, DT_I16>(mode, p, stream);

@@ -1,0 +1,481 @@
+// Quality measures of the block transform (sections 4.1 and 5.1):
+//
+//   moments     per image, over its tiles, the sum and the sum of squares of
+//               every coefficient b[v][u] of B = T A T^T, and the sum and sum
+//               of squares of the (level-shifted) pixels.  These are exact
+//               integers; the measured coding gain follows from them.
+//   coding gain (measured) the unified coding gain of the separable 2D
+//               transform with the model's covariances replaced by the
+//               variances measured over an image's tiles, in float32.
+//   coding gain (AR(1)) the closed form of section 4.1 under the first-order
+//               Markov model, and the KLT's, for many correlation values at
+//               once, in float32.
+//   PSNR        10 log10(255^2 H W / SSE) per image, in float32.
+//
+// The moment kernel reuses the row-group code of the 16/32-point kernels: a
+// 256-thread workgroup transforms 256/N horizontally adjacent tiles (row
+// pass, LDS exchange, column pass) and stages all N^2 coefficients of each
+// tile in LDS.  Thread t then owns coefficient positions t, t + 256, ...
+// (N >= 16) or position t mod 64 of every fourth tile (N = 8) and keeps
+// running sums of them in registers while the workgroup walks its share of
+// the image's tile groups; one set of 64-bit atomics per workgroup adds them
+// to the image's record.  Squares are split into their low and high 32-bit
+// halves, each summed in 64 bits, so every sum is exact for any int16 input.
+#include "jam_group.hpp"
+
+namespace adct {
+namespace {
+
+using namespace jam;
+
+// ------------------------------------------------------- transform constants
+// T_N, diag(T T^T) and the norms behind B_k, all from the butterflies at
+// compile time (U = N T^-1 is half of the inverse chain K_N).
+template <int N>
+struct TransformInfo {
+  int8_t t[N][N];        // T_N, row-major
+  int32_t d[N];          // diag(T T^T)
+  int32_t ucol2[N];      // sum_j U[j][k]^2: squared norm of column k of U
+  int64_t urow2d[N];     // sum_j U[k][j]^2 d_j
+  int32_t l1max;         // largest row sum of |T[v][i]|
+};
+
+template <int KIND, int N>
+constexpr TransformInfo<N> make_info() {
+  TransformInfo<N> I{};
+  int u[N][N] = {};
+  for (int j = 0; j < N; ++j) {
+    int e[N] = {};
+    e[j] = 1;
+    fwdN<KIND, N>(e);
+    for (int v = 0; v < N; ++v) I.t[v][j] = static_cast<int8_t>(e[v]);
+    int f[N] = {};
+    f[j] = 1;
+    invN<KIND, N>(f);
+    for (int v = 0; v < N; ++v) u[v][j] = f[v] / 2;
+  }
+  I.l1max = 0;
+  for (int v = 0; v < N; ++v) {
+    int d = 0, l1 = 0, c2 = 0;
+    for (int i = 0; i < N; ++i) {
+      d += I.t[v][i] * I.t[v][i];
+      l1 += I.t[v][i] < 0 ? -I.t[v][i] : I.t[v][i];
+      c2 += u[i][v] * u[i][v];
+    }
+    I.d[v] = d;
+    I.ucol2[v] = c2;
+    if (l1 > I.l1max) I.l1max = l1;
+  }
+  for (int v = 0; v < N; ++v) {
+    int64_t s = 0;
+    for (int i = 0; i < N; ++i) s += static_cast<int64_t>(u[v][i]) * u[v][i] * I.d[i];
+    I.urow2d[v] = s;
+  }
+  return I;
+}
+
+static __constant__ TransformInfo<8> kInfo1_8 = make_info<KIND_SIGN, 8>();
+static __constant__ TransformInfo<16> kInfo1_16 = make_info<KIND_SIGN, 16>();
+static __constant__ TransformInfo<32> kInfo1_32 = make_info<KIND_SIGN, 32>();
+static __constant__ TransformInfo<8> kInfo2_8 = make_info<KIND_ROUND, 8>();
+static __constant__ TransformInfo<16> kInfo2_16 = make_info<KIND_ROUND, 16>();
+static __constant__ TransformInfo<32> kInfo2_32 = make_info<KIND_ROUND, 32>();
+static __constant__ TransformInfo<8> kInfoWHT = make_info<KIND_WHT, 8>();
+static __constant__ TransformInfo<8> kInfoSDCT = make_info<KIND_SDCT, 8>();
+static __constant__ TransformInfo<8> kInfoHT = make_info<KIND_HT, 8>();
+
+template <int KIND, int N>
+__device__ __forceinline__ const TransformInfo<N>& info() {
+  if constexpr (KIND == KIND_WHT) {
+    return kInfoWHT;
+  } else if constexpr (KIND == KIND_SDCT) {
+    return kInfoSDCT;
+  } else if constexpr (KIND == KIND_HT) {
+    return kInfoHT;
+  } else if constexpr (KIND == KIND_SIGN) {
+    if constexpr (N == 8) return kInfo1_8;
+    else if constexpr (N == 16) return kInfo1_16;
+    else return kInfo1_32;
+  } else {
+    if constexpr (N == 8) return kInfo2_8;
+    else if constexpr (N == 16) return kInfo2_16;
+    else return kInfo2_32;
+  }
+}
+
+// B_k of section 4.1 times the 1/d_k that the scale s_k^2 contributes to A_k,
+// for the columns (synthesis basis) or the rows of C^-1 = (U / N) S^-1:
+//   columns: B_k / d_k = ucol2[k] / N^2,   rows: B_k / d_k = urow2d[k] / (N^2 d_k).
+template <int KIND, int N>
+__device__ __forceinline__ float basis_factor(int k, int basis) {
+  const TransformInfo<N>& I = info<KIND, N>();
+  constexpr float inv_n2 = 1.0f / static_cast<float>(N * N);
+  return basis == ADCT_BASIS_COLS
+             ? static_cast<float>(I.ucol2[k]) * inv_n2
+             : static_cast<float>(I.urow2d[k]) / static_cast<float>(I.d[k]) * inv_n2;
+}
+
+// ------------------------------------------------------------------ moments
+struct MomParams {
+  const void* src;
+  Geom g;
+  unsigned long long* mom;   // [batch][moment_words(N)]
+  int wpi;                   // workgroups per image
+};
+
+// Every |b| of 8-bit input is at most 128 l1max^2; when that is below 2^15
+// the square fits a 24-bit multiply and has no high half.
+template <int KIND, int N, int DT>
+constexpr bool small_squares() {
+  constexpr TransformInfo<N> I = make_info<KIND, N>();
+  return DT == DT_U8 && 128 * I.l1max * I.l1max < 32768;
+}
+
+template <int KIND, int N, int DT>
+__global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
+  using C = Cfg<N>;
+  constexpr int NN = N * N;
+  constexpr int PPT = NN >= kBlock ? NN / kBlock : 1;      // positions per thread
+  constexpr int KSTEP = NN >= kBlock ? 1 : kBlock / NN;    // tiles between a thread's tiles
+  constexpr bool SMALL = small_squares<KIND, N, DT>();
+  constexpr int RED = KSTEP > 1 ? 6 * kBlock : 0;          // int words of the N = 8 reduction
+  __shared__ __align__(16) int S[C::WORDS > RED ? C::WORDS : RED];
+  __shared__ long long red_a[kBlock / 64][2];
+
+  const int img = blockIdx.y;
+  const int t = threadIdx.x;
+  const int a_idx = t / C::TPW, k = t % C::TPW;
+  const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
+  const int64_t groups = static_cast<int64_t>(groups_x) * p.g.tiles_y;
+  const int p0 = NN >= kBlock ? t : t % NN;
+  const int k0 = NN >= kBlock ? 0 : t / NN;
+
+  long long s1[PPT];
+  unsigned long long s2lo[PPT], s2hi[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    s1[q] = 0;
+    s2lo[q] = 0;
+    s2hi[q] = 0;
+  }
+  long long a1 = 0;
+  unsigned long long a2 = 0;
+  long long tiles = 0;
+
+  GroupIO io{};
+  io.src = p.src;
+  io.pitch = p.g.pitch;
+  for (int64_t q = blockIdx.x; q < groups; q += p.wpi) {
+    const int ty = static_cast<int>(q / groups_x);
+    const int tx0 = static_cast<int>(q - static_cast<int64_t>(ty) * groups_x) * C::TPW;
+    const int nact = min(C::TPW, p.g.tiles_x - tx0);
+    io.active = k < nact;
+    io.tile_pix = static_cast<int64_t>(img) * p.g.image_stride +
+                  static_cast<int64_t>(ty) * N * p.g.pitch + static_cast<int64_t>(tx0 + k) * N;
+    RowWords<N, DT> x;
+    row_forward<KIND, N, DT, kBlock>(S, io, a_idx, k, x);
+    if (io.active) {   // pixel sums of this row, level-shifted for 8-bit input
+      if constexpr (DT == DT_U8) {
+        uint32_t sx = 0, sxx = 0;
+#pragma unroll
+        for (int d = 0; d < RowWords<N, DT>::W; ++d) {
+          sx = __builtin_amdgcn_udot4(x.w[d], 0x01010101u, sx, false);
+          sxx = __builtin_amdgcn_udot4(x.w[d], x.w[d], sxx, false);
+        }
+        // a = x - 128: sum a = sum x - 128 N, sum a^2 = sum x^2 - 256 sum x + 128^2 N
+        a1 += static_cast<long long>(sx) - 128 * N;
+        a2 += static_cast<unsigned long long>(sxx) + 16384ull * N - 256ull * sx;
+      } else {
+        int xv[N];
+        unpack_row<N, DT>(x, xv);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          a1 += xv[i];
+          a2 += static_cast<unsigned long long>(static_cast<long long>(xv[i]) * xv[i]);
+        }
+      }
+    }
+    __syncthreads();
+    int c[N];
+    read_column<N, kBlock>(S, a_idx, k, c);
+    fwdN<KIND, N>(c);
+    if constexpr (DT == DT_U8)
+      if (a_idx == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
+    __syncthreads();
+    write_column_rows<N, kBlock>(S, a_idx, k, c);   // padded [k][v][u]
+    __syncthreads();
+#pragma unroll
+    for (int pq = 0; pq < PPT; ++pq) {
+      const int pos = p0 + pq * kBlock;
+      const int off = (pos / N) * C::CS + pos % N;
+      for (int kk = k0; kk < nact; kk += KSTEP) {
+        const int b = S[kk * C::TS + off];
+        s1[pq] += b;
+        if constexpr (SMALL) {
+          s2lo[pq] += static_cast<uint32_t>(__mul24(b, b));
+        } else {
+          const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
+          s2lo[pq] += static_cast<uint32_t>(sq);
+          s2hi[pq] += sq >> 32;
+        }
+      }
+    }
+    tiles += nact;
+    __syncthreads();   // S is rewritten by the next group
+  }
+
+  unsigned long long* rec = p.mom + static_cast<int64_t>(img) * (3 * NN + 4);
+  if constexpr (KSTEP > 1) {
+    // N = 8: threads t, t + 64, t + 128, t + 192 hold the same position
+    unsigned long long* R = reinterpret_cast<unsigned long long*>(S);
+    R[t] = static_cast<unsigned long long>(s1[0]);
+    R[kBlock + t] = s2lo[0];
+    R[2 * kBlock + t] = s2hi[0];
+    __syncthreads();
+    if (t < NN) {
+      unsigned long long v1 = 0, vlo = 0, vhi = 0;
+#pragma unroll
+      for (int m = 0; m < KSTEP; ++m) {
+        v1 += R[t + m * NN];
+        vlo += R[kBlock + t + m * NN];
+        vhi += R[2 * kBlock + t + m * NN];
+      }
+      if (v1 != 0) atomicAdd(rec + t, v1);
+      if (vlo != 0) atomicAdd(rec + NN + t, vlo);
+      if (vhi != 0) atomicAdd(rec + 2 * NN + t, vhi);
+    }
+  } else {
+#pragma unroll
+    for (int pq = 0; pq < PPT; ++pq) {
+      const int pos = p0 + pq * kBlock;
+      if (s1[pq] != 0) atomicAdd(rec + pos, static_cast<unsigned long long>(s1[pq]));
+      if (s2lo[pq] != 0) atomicAdd(rec + NN + pos, s2lo[pq]);
+      if (s2hi[pq] != 0) atomicAdd(rec + 2 * NN + pos, s2hi[pq]);
+    }
+  }
+  // pixel sums: wave, then workgroup
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a1 += __shfl_xor(a1, off, 64);
+    a2 += __shfl_xor(a2, off, 64);
+  }
+  if ((t & 63) == 0) {
+    red_a[t >> 6][0] = a1;
+    red_a[t >> 6][1] = static_cast<long long>(a2);
+  }
+  __syncthreads();
+  if (t == 0 && tiles > 0) {
+    long long b1 = 0;
+    unsigned long long b2 = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      b1 += red_a[w][0];
+      b2 += static_cast<unsigned long long>(red_a[w][1]);
+    }
+    atomicAdd(rec + 3 * NN, static_cast<unsigned long long>(tiles));
+    atomicAdd(rec + 3 * NN + 1, static_cast<unsigned long long>(tiles) * NN);
+    if (b1 != 0) atomicAdd(rec + 3 * NN + 2, static_cast<unsigned long long>(b1));
+    if (b2 != 0) atomicAdd(rec + 3 * NN + 3, b2);
+  }
+}
+
+// ----------------------------------------------------- measured coding gain
+// count * s2 - s1^2 = count^2 times the population variance, exactly (128-bit)
+__device__ __forceinline__ float scaled_variance(unsigned long long count, unsigned long long s2lo,
+                                                 unsigned long long s2hi, long long s1) {
+  const unsigned __int128 s2 = (static_cast<unsigned __int128>(s2hi) << 32) + s2lo;
+  const unsigned long long m = static_cast<unsigned long long>(s1 < 0 ? -s1 : s1);
+  const unsigned __int128 v = static_cast<unsigned __int128>(count) * s2 -
+                              static_cast<unsigned __int128>(m) * m;
+  const float hi = static_cast<float>(static_cast<unsigned long long>(v >> 64));
+  const float lo = static_cast<float>(static_cast<unsigned long long>(v));
+  return fmaf(hi, 18446744073709551616.0f, lo);
+}
+
+// One workgroup per record.  A_vu B_v B_u = (var_b / var_x) f_v f_u with
+// f the basis factors above; the gain is -10/N^2 sum log10 of that.
+template <int KIND, int N>
+__global__ __launch_bounds__(kBlock) void coding_gain_kernel(const unsigned long long* mom,
+                                                             int basis, float* cg) {
+  constexpr int NN = N * N;
+  __shared__ float red[kBlock / 64];
+  __shared__ int zero_var[kBlock / 64];
+  const unsigned long long* rec = mom + static_cast<int64_t>(blockIdx.x) * (3 * NN + 4);
+  const unsigned long long tiles = rec[3 * NN], pixels = rec[3 * NN + 1];
+  const float vx = scaled_variance(pixels, rec[3 * NN + 3], 0ull, static_cast<long long>(rec[3 * NN + 2]));
+  const float fp = static_cast<float>(pixels), ft = static_cast<float>(tiles);
+  // var_b / var_x = (Vb / tiles^2) / (Vx / pixels^2)
+  const float ratio = (fp / ft) * (fp / ft) / vx;
+  float sum = 0.0f;
+  int zeros = 0;
+  for (int pos = threadIdx.x; pos < NN; pos += kBlock) {
+    const float vb = scaled_variance(tiles, rec[NN + pos], rec[2 * NN + pos],
+                                     static_cast<long long>(rec[pos]));
+    if (vb == 0.0f) ++zeros;
+    else sum += log10f(vb * ratio * (basis_factor<KIND, N>(pos / N, basis) *
+                                     basis_factor<KIND, N>(pos % N, basis)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off, 64);
+    zeros += __shfl_xor(zeros, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = sum;
+    zero_var[threadIdx.x >> 6] = zeros;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.0f;
+    int z = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      s += red[w];
+      z += zero_var[w];
+    }
+    float g;
+    if (tiles == 0 || vx == 0.0f) g = __builtin_nanf("");
+    else if (z > 0) g = INFINITY;
+    else g = -10.0f / static_cast<float>(NN) * s;
+    cg[blockIdx.x] = g;
+  }
+}
+
+// ------------------------------------------------- AR(1) model coding gain
+// One wave per correlation value rho; lane k < N evaluates A_k B_k.  With
+// h row k of T, h R h^T for R[m][n] = rho^|m-n| is evaluated in the
+// innovations form of the first-order Markov process (x_0 = w_0,
+// x_n = rho x_(n-1) + sqrt(1 - rho^2) w_n): with z_j = sum_(n>=j) rho^(n-j) h_n,
+//   h R h^T = z_0^2 + (1 - rho^2) sum_(j>=1) z_j^2,
+// a sum of non-negative terms, which stays accurate as rho -> 1 where the
+// entries of R nearly cancel against the zero-sum AC rows.  The KLT's gain
+// is -10/N log10 det R with det R = (1 - rho^2)^(N-1).
+template <int KIND, int N>
+__global__ __launch_bounds__(64) void coding_gain_ar1_kernel(const float* rho, int count,
+                                                             int basis, float* cg, float* cg_klt) {
+  const int i = blockIdx.x;
+  const int k = threadIdx.x;
+  const float r = rho[i];
+  float term = 0.0f;
+  if (k < N) {
+    const TransformInfo<N>& I = info<KIND, N>();
+    float z = 0.0f, acc = 0.0f;
+    for (int n = N - 1; n >= 1; --n) {
+      z = fmaf(r, z, static_cast<float>(I.t[k][n]));
+      acc = fmaf(z, z, acc);
+    }
+    z = fmaf(r, z, static_cast<float>(I.t[k][0]));
+    const float one_minus_r2 = (1.0f - r) * (1.0f + r);
+    const float hrh = fmaf(one_minus_r2, acc, z * z);
+    term = log10f(hrh * basis_factor<KIND, N>(k, basis));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
+  if (k == 0) {
+    if (cg != nullptr) cg[i] = -10.0f / static_cast<float>(N) * term;
+    if (cg_klt != nullptr)
+      cg_klt[i] = -10.0f * static_cast<float>(N - 1) / static_cast<float>(N) *
+                  (log1pf(-r * r) * 0.43429448190325182f);
+  }
+}
+
+// -------------------------------------------------------------------- PSNR
+__global__ void psnr_plain_kernel(const unsigned long long* sse, int count, float npix, float* psnr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const unsigned long long e = sse[i];
+  psnr[i] = e == 0ull ? INFINITY : 10.0f * log10f(65025.0f * npix / static_cast<float>(e));
+}
+
+template <int KIND, int N>
+hipError_t launch_moments_typed(int dtype, const MomParams& p, hipStream_t s) {
+  const dim3 grid(p.wpi, p.g.batch);
+  if (dtype == DT_U8) moments_kernel<KIND, N, DT_U8><<<grid, kBlock, 0, s>>>(p);
+  else moments_kernel<KIND, N, DT_I16><<<grid, kBlock, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_cg_typed(int n, const unsigned long long* mom, int count, int basis, float* cg,
+                           hipStream_t s) {
+  if (n == 8) coding_gain_kernel<KIND, 8><<<count, kBlock, 0, s>>>(mom, basis, cg);
+  else if (n == 16) coding_gain_kernel<KIND, 16><<<count, kBlock, 0, s>>>(mom, basis, cg);
+  else coding_gain_kernel<KIND, 32><<<count, kBlock, 0, s>>>(mom, basis, cg);
+  return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_ar1_typed(int n, const float* rho, int count, int basis, float* cg,
+                            float* cg_klt, hipStream_t s) {
+  if (n == 8) coding_gain_ar1_kernel<KIND, 8><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+  else if (n == 16) coding_gain_ar1_kernel<KIND, 16><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+  else coding_gain_ar1_kernel<KIND, 32><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
+                   unsigned long long* mom, hipStream_t s) {
+  MomParams p;
+  p.src = src;
+  p.g = g;
+  p.mom = mom;
+  const int tpw = kBlock / n;
+  const int64_t groups = static_cast<int64_t>((g.tiles_x + tpw - 1) / tpw) * g.tiles_y;
+  // about 2048 workgroups in all (8 per CU), each walking its image's groups
+  // with stride wpi; at least one group each
+  int64_t wpi = (2048 + g.batch - 1) / g.batch;
+  if (wpi > groups) wpi = groups;
+  if (wpi < 1) wpi = 1;
+  p.wpi = static_cast<int>(wpi);
+  if (kind == KIND_WHT) return launch_moments_typed<KIND_WHT, 8>(dtype, p, s);
+  if (kind == KIND_SDCT) return launch_moments_typed<KIND_SDCT, 8>(dtype, p, s);
+  if (kind == KIND_HT) return launch_moments_typed<KIND_HT, 8>(dtype, p, s);
+  if (kind == KIND_SIGN) {
+    if (n == 8) return launch_moments_typed<KIND_SIGN, 8>(dtype, p, s);
+    if (n == 16) return launch_moments_typed<KIND_SIGN, 16>(dtype, p, s);
+    return launch_moments_typed<KIND_SIGN, 32>(dtype, p, s);
+  }
+  if (n == 8) return launch_moments_typed<KIND_ROUND, 8>(dtype, p, s);
+  if (n == 16) return launch_moments_typed<KIND_ROUND, 16>(dtype, p, s);
+  return launch_moments_typed<KIND_ROUND, 32>(dtype, p, s);
+}
+
+int launch_coding_gain(int kind, int n, int basis, const unsigned long long* mom, int count,
+                       float* cg, hipStream_t s) {
+  switch (kind) {
+    case KIND_WHT: coding_gain_kernel<KIND_WHT, 8><<<count, kBlock, 0, s>>>(mom, basis, cg); break;
+    case KIND_SDCT: coding_gain_kernel<KIND_SDCT, 8><<<count, kBlock, 0, s>>>(mom, basis, cg); break;
+    case KIND_HT: coding_gain_kernel<KIND_HT, 8><<<count, kBlock, 0, s>>>(mom, basis, cg); break;
+    case KIND_SIGN: return launch_cg_typed<KIND_SIGN>(n, mom, count, basis, cg, s);
+    default: return launch_cg_typed<KIND_ROUND>(n, mom, count, basis, cg, s);
+  }
+  return hipGetLastError();
+}
+
+int launch_coding_gain_ar1(int kind, int n, int basis, const float* rho, int count, float* cg,
+                           float* cg_klt, hipStream_t s) {
+  switch (kind) {
+    case KIND_WHT:
+      coding_gain_ar1_kernel<KIND_WHT, 8><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+      break;
+    case KIND_SDCT:
+      coding_gain_ar1_kernel<KIND_SDCT, 8><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+      break;
+    case KIND_HT:
+      coding_gain_ar1_kernel<KIND_HT, 8><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+      break;
+    case KIND_SIGN: return launch_ar1_typed<KIND_SIGN>(n, rho, count, basis, cg, cg_klt, s);
+    default: return launch_ar1_typed<KIND_ROUND>(n, rho, count, basis, cg, cg_klt, s);
+  }
+  return hipGetLastError();
+}
+
+int launch_psnr(const unsigned long long* sse, int count, int64_t pixels, float* psnr,
+                hipStream_t s) {
+  psnr_plain_kernel<<<(count + 255) / 256, 256, 0, s>>>(sse, count, static_cast<float>(pixels), psnr);
+  return hipGetLastError();
+}
+
+}  // namespace adct

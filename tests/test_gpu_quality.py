@@ -1,0 +1,175 @@
+"""GPU parity of the quality measures: coefficient moments (bit-exact), the
+measured 2D coding gain, the AR(1) coding gain and PSNR (float32 within
+1e-5 relative of the float64 oracle).
+
+Tolerance of the float32 gains: |got - want| <= 1e-5 * max(|want|, 1 dB).  A
+coding gain can cross zero (a non-orthogonal transform at rho -> 0), where
+no relative bound is attainable; above 1 dB in magnitude the bound is the
+plain 1e-5 relative one."""
+import numpy as np
+import pytest
+
+from oracle import matrices as M
+from oracle import metrics as MT
+from oracle import pipeline as P
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only runs deselect these
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2207_11638_amd as adct  # noqa: E402
+
+DEV = torch.device("cuda:0")
+RTOL = 1e-5
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def close(got, want):
+    return abs(float(got) - float(want)) <= RTOL * max(abs(float(want)), 1.0)
+
+
+def record_matches(rec, mom, n):
+    """A device moment record against the oracle's exact sums."""
+    nn = n * n
+    rec = [int(v) for v in rec]
+    s1 = [(v - (1 << 64)) if v >= (1 << 63) else v for v in rec[:nn]]
+    s2 = [rec[2 * nn + p] * (1 << 32) + rec[nn + p] for p in range(nn)]
+    a1 = rec[3 * nn + 2]
+    a1 = a1 - (1 << 64) if a1 >= (1 << 63) else a1
+    return (s1 == [int(v) for v in mom["s1"].reshape(-1)] and
+            s2 == [int(v) for v in mom["s2"].reshape(-1)] and
+            rec[3 * nn] == mom["tiles"] and rec[3 * nn + 1] == mom["pixels"] and
+            a1 == mom["a1"] and rec[3 * nn + 3] == mom["a2"])
+
+
+# shapes: several workgroups per tile row with a partial last group, and
+# more tile groups than the walking workgroups of one image
+SHAPES = {8: (72, 8 * 75), 16: (80, 16 * 21), 32: (96, 32 * 11)}
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("dtype", ["u8", "i16"])
+def test_moments_match_oracle(kind, n, dtype):
+    h, w = SHAPES[n]
+    if dtype == "u8":
+        imgs = [synth.ar1_image(h, w, rho=0.9 + 0.03 * i, seed=500 + i) for i in range(3)]
+    else:
+        imgs = [synth.laplace_residual(h, w, seed=600 + i) for i in range(3)]
+    mom = host(adct.moments(to_dev(np.stack(imgs)), kind, n))
+    for i, im in enumerate(imgs):
+        assert record_matches(mom[i], P.coefficient_moments(im, kind, n), n), (i, kind, n)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_moments_full_int16_range(n):
+    """Tiles of +-32767 / -32768: the squares use their high halves."""
+    rng = np.random.default_rng(7)
+    h, w = 2 * n, 5 * n
+    img = np.where(rng.random((h, w)) < 0.5, -32768, 32767).astype(np.int16)
+    img[:n, :n] = 32767
+    for kind in M.KINDS:
+        mom = host(adct.moments(to_dev(img), kind, n))
+        assert record_matches(mom[0], P.coefficient_moments(img, kind, n), n)
+
+
+def test_moments_accumulate_over_calls():
+    img = synth.ar1_image(64, 256, rho=0.95, seed=11)
+    x = to_dev(img)
+    out = adct.moments(x, 2, 8)
+    adct.moments(x, 2, 8, out=out)
+    got = host(out)[0].astype(object)
+    once = host(adct.moments(x, 2, 8))[0].astype(object)
+    assert all(int(a) == (2 * int(b)) % (1 << 64) for a, b in zip(got, once))
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("basis", ["rows", "cols"])
+def test_measured_coding_gain(kind, n, basis):
+    h, w = SHAPES[n]
+    imgs = [synth.ar1_image(h, w, rho=rho, seed=700 + i) for i, rho in enumerate((0.85, 0.95, 0.98))]
+    imgs.append(synth.laplace_residual(h, w, seed=710).astype(np.int16))
+    for im in imgs:
+        mom = adct.moments(to_dev(im), kind, n)
+        got = host(adct.coding_gain(mom, kind, n, basis))[0]
+        want = P.empirical_coding_gain(im, kind, n, basis)
+        assert close(got, want), (got, want, im.dtype)
+
+
+def test_measured_coding_gain_edge_cases():
+    # every tile identical: each coefficient is constant -> +inf
+    tile = synth.ar1_image(8, 8, rho=0.9, seed=3)
+    img = np.tile(tile, (6, 9))
+    got = host(adct.coding_gain(adct.moments(to_dev(img), 1, 8), 1, 8))[0]
+    assert np.isinf(got) and got > 0
+    assert np.isinf(P.empirical_coding_gain(img, 1, 8))
+    # constant image: the pixel variance is zero -> NaN
+    flat = np.full((16, 32), 77, dtype=np.uint8)
+    got = host(adct.coding_gain(adct.moments(to_dev(flat), 2, 8), 2, 8))[0]
+    assert np.isnan(got) and np.isnan(P.empirical_coding_gain(flat, 2, 8))
+    # an empty record (all zero) -> NaN
+    empty = torch.zeros((1, 3 * 64 + 4), dtype=torch.uint64, device=DEV)
+    assert np.isnan(host(adct.coding_gain(empty, 1, 8))[0])
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("basis", ["rows", "cols"])
+def test_ar1_coding_gain(kind, n, basis):
+    rhos = np.array([0.0, 0.05, 0.3, 0.5, 0.75, 0.85, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999],
+                    dtype=np.float32)
+    cg, klt = adct.coding_gain_ar1(to_dev(rhos), kind, n, basis)
+    cg, klt = host(cg), host(klt)
+    c = M.near_orthogonal(kind, n)
+    for i, rho in enumerate(rhos.astype(np.float64)):
+        want = MT.coding_gain(c, rho, basis)
+        assert close(cg[i], want), (rho, cg[i], want)
+        want_klt = MT.klt_coding_gain(n, rho)
+        assert close(klt[i], want_klt), (rho, klt[i], want_klt)
+
+
+def test_ar1_coding_gain_sweep_many_values():
+    """A long sweep (many workgroups) over rho in [0, 1)."""
+    rhos = np.linspace(0.0, 0.999, 2001, dtype=np.float32)
+    cg, klt = adct.coding_gain_ar1(to_dev(rhos), 2, 8, "cols")
+    cg, klt = host(cg), host(klt)
+    c = M.near_orthogonal(2, 8)
+    for i in range(0, len(rhos), 97):
+        rho = float(rhos[i])
+        assert close(cg[i], MT.coding_gain(c, rho, "cols"))
+        assert close(klt[i], MT.klt_coding_gain(8, rho))
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_psnr_matches_oracle(n):
+    h, w = SHAPES[n]
+    imgs = [synth.ar1_image(h, w, rho=0.95, seed=800 + i) for i in range(4)]
+    x = to_dev(np.stack(imgs))
+    out = adct.compress(x, 2, n, 10)
+    ps = host(adct.psnr(out["sse"], h * w))
+    for i, im in enumerate(imgs):
+        want = P.compress(im, 2, n, 10)
+        assert close(ps[i], want["psnr"]), (ps[i], want["psnr"])
+    full = adct.compress(x, 1, n, n * n)
+    assert np.all(np.isinf(host(adct.psnr(full["sse"], h * w))))
+
+
+def test_quality_calls_reject_bad_arguments():
+    rho = to_dev(np.array([0.5], dtype=np.float32))
+    with pytest.raises(ValueError):
+        adct.coding_gain_ar1(rho, 1, 8, "diagonal")
+    with pytest.raises(adct.AdctError):
+        adct.coding_gain_ar1(rho, 3, 8)
+    with pytest.raises(adct.AdctError):
+        adct.moments(to_dev(np.zeros((12, 16), np.uint8)), 1, 8)   # 12 rows: not a multiple of 8

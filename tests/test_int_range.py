@@ -34,7 +34,51 @@ class Forms:
         return v
 
 
+def hadamard8(x, sequency, t):
+    y = [t(x[i] + x[i + 4]) for i in range(4)] + [t(x[i] - x[i + 4]) for i in range(4)]
+    z = [None] * 8
+    for h in range(2):
+        for i in range(2):
+            z[4 * h + i] = t(y[4 * h + i] + y[4 * h + i + 2])
+            z[4 * h + i + 2] = t(y[4 * h + i] - y[4 * h + i + 2])
+    nat = [None] * 8
+    for q in range(4):
+        nat[2 * q] = t(z[2 * q] + z[2 * q + 1])
+        nat[2 * q + 1] = t(z[2 * q] - z[2 * q + 1])
+    return [nat[i] for i in (0, 4, 6, 2, 3, 7, 5, 1)] if sequency else nat
+
+
+def hadamard8_inv(X, sequency, t):
+    nat = [None] * 8
+    if sequency:
+        for k, i in enumerate((0, 4, 6, 2, 3, 7, 5, 1)):
+            nat[i] = X[k]
+    else:
+        nat = list(X)
+    return [t(2 * v) for v in hadamard8(nat, False, t)]
+
+
+def sdct8(x, t):
+    s = [t(x[i] + x[7 - i]) for i in range(4)]
+    d = [t(x[i] - x[7 - i]) for i in range(4)]
+    e0, e1, e2, e3 = t(s[0] + s[3]), t(s[1] + s[2]), t(s[0] - s[3]), t(s[1] - s[2])
+    a, b, c, p = t(d[0] - d[1]), t(d[2] + d[3]), t(d[2] - d[3]), t(d[0] + d[1])
+    return [t(e0 + e1), t(p + b), t(e2 + e3), t(a - b), t(e0 - e1), t(a + b), t(e2 - e3),
+            t(a + c)]
+
+
+def sdct8_inv(X, t):
+    f0, f1, f2, f3 = t(X[0] + X[4]), t(X[0] - X[4]), t(X[2] + X[6]), t(X[2] - X[6])
+    s = [t(2 * (f0 + f2)), t(2 * (f1 + f3)), t(2 * (f1 - f3)), t(2 * (f0 - f2))]
+    d = [t(4 * (X[1] + X[3])), t(4 * (X[1] - X[5])), t(4 * (X[7] - X[3])), t(4 * (X[5] - X[7]))]
+    return [t(s[i] + d[i]) for i in range(4)] + [t(s[3 - i] - d[3 - i]) for i in range(4)]
+
+
 def fwd8(x, kind, t):
+    if kind in (M.WHT, M.HT):
+        return hadamard8(x, kind == M.WHT, t)
+    if kind == M.SDCT:
+        return sdct8(x, t)
     y = [t(x[0] + x[7]), t(x[1] + x[6]), t(x[2] + x[5]), t(x[3] + x[4]),
          t(x[3] - x[4]), t(x[2] - x[5]), t(x[1] - x[6]), t(x[0] - x[7])]
     z0, z1, z2, z3 = t(y[0] + y[3]), t(y[1] + y[2]), t(y[1] - y[2]), t(y[0] - y[3])
@@ -48,6 +92,10 @@ def fwd8(x, kind, t):
 
 
 def inv8(X, kind, t):
+    if kind in (M.WHT, M.HT):
+        return hadamard8_inv(X, kind == M.WHT, t)
+    if kind == M.SDCT:
+        return sdct8_inv(X, t)
     v0, v1, v2, v3, v4, v5, v6, v7 = X[0], X[2], X[4], X[6], X[1], X[5], X[3], X[7]
     w0, w1, w2, w3 = t(2 * v0), t(2 * v2), t(2 * v3), t(2 * v1)
     w4, w7 = (t(v4 + v7), t(v4 - v7)) if kind == M.SIGN else (t(2 * v4), t(-2 * v7))
@@ -111,16 +159,17 @@ def inverse_peaks(kind, n, w):
     return cols, rows
 
 
-@pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", [8, 16, 32])
+KIND_N = [(k, n) for k in M.KINDS for n in (8, 16, 32)] + [(k, 8) for k in M.COMPARISON_KINDS]
+
+
+@pytest.mark.parametrize("kind,n", KIND_N)
 def test_model_computes_the_transform_and_its_inverse(kind, n):
     t = Forms()
     assert np.array_equal(np.array(fwd(unit(n), kind, t)), M.transform_matrix(kind, n))
     assert np.array_equal(np.array(inv(unit(n), kind, t)), 2 * M.scaled_inverse(kind, n))
 
 
-@pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("kind,n", KIND_N)
 def test_zonal_path_fits_int32_for_full_range_int16(kind, n):
     T = M.transform_matrix(kind, n)
     row = peak(fwd, unit(n), kind)
@@ -167,5 +216,33 @@ def test_quantised_path_fits_int32_for_full_range_int16(kind, n):
         row = row_lin * XMAX + (W @ ((outs @ e) / 2 + 0.5).T).max()
         assert max(col, row) <= INT32, (q, col, row)
         # 24-bit products of the dequantiser are exact
+        bmax = np.abs(T).sum(1).max() ** 2 * XMAX
+        assert bmax * mq.max() / 2 ** 24 + 1 < 2 ** 23 and dq.max() < 2 ** 23
+
+
+@pytest.mark.parametrize("kind", M.KINDS + M.COMPARISON_KINDS)
+def test_quantised_8point_path_fits_int32_for_full_range_int16(kind):
+    # N = 8 keeps the dequantised values' fractional bit through both inverse
+    # passes (no halving between them): bound b~ = 2 rho b + e directly
+    n = 8
+    T = M.transform_matrix(kind, n).astype(np.float64)
+    d = np.diag(T @ T.T)
+    forms = []
+
+    def collect(v):
+        forms.append(np.abs(v))
+        return v
+    outs = np.abs(np.array(inv(unit(n), kind, collect)))
+    W = np.array(forms)
+    for q in (1, 16, 4096):
+        g = q * np.sqrt(np.outer(d, d))
+        mq = np.vectorize(lambda x: round_half_away(2 ** 24 / x))(g)
+        dq = np.vectorize(lambda x: round_half_away(2 * x))(g)
+        rho = mq * dq / 2 ** 25
+        e = dq / 2
+        col_lin, row_lin = inverse_peaks(kind, n, 2 * rho)
+        col = col_lin * XMAX + (W @ e).max()
+        row = row_lin * XMAX + (W @ (outs @ e).T).max()
+        assert max(col, row) <= INT32, (q, col, row)
         bmax = np.abs(T).sum(1).max() ** 2 * XMAX
         assert bmax * mq.max() / 2 ** 24 + 1 < 2 ** 23 and dq.max() < 2 ** 23

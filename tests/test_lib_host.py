@@ -34,6 +34,17 @@ def test_library_butterflies_compute_the_paper_matrices(kind, n):
     assert np.array_equal(adct.get_matrix(kind, n, inverse=True), M.scaled_inverse(kind, n))
 
 
+@pytest.mark.parametrize("kind", M.COMPARISON_KINDS)
+def test_library_butterflies_compute_the_comparison_matrices(kind, lib):
+    # WHT, SDCT and HT of section 4: the add-only butterflies reproduce the
+    # matrices and their exact integer inverses 8 T^-1; they are 8-point only
+    assert np.array_equal(adct.get_matrix(kind, 8), M.transform_matrix(kind, 8))
+    assert np.array_equal(adct.get_matrix(kind, 8, inverse=True), M.scaled_inverse(kind, 8))
+    out = np.zeros(256, dtype=np.int32)
+    assert lib.adct_get_matrix(kind, 16, 0, out.ctypes.data) == -1
+    assert np.allclose(adct.scale_vector(kind, 8), M.scale_vector(kind, 8), rtol=0, atol=0)
+
+
 @pytest.mark.parametrize("n", M.SIZES)
 def test_zigzag_table(n):
     want = [v * n + u for v, u in M.zigzag(n)]
@@ -68,7 +79,8 @@ def _compress(lib, **kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(transform=3), -1), (dict(transform=0), -1), (dict(n=4), -1), (dict(n=64), -1),
+    (dict(transform=6), -1), (dict(transform=0), -1), (dict(transform=3, n=16), -1),
+    (dict(transform=4, n=32), -1), (dict(n=4), -1), (dict(n=64), -1),
     (dict(r=0), -1), (dict(r=65), -1), (dict(n=16, r=257), -1), (dict(qstep=-1), -1),
     (dict(qstep=4097), -1), (dict(dtype=2), -1), (dict(src=None), -1),
     (dict(height=60), -2), (dict(width=20, pitch=20), -2), (dict(pitch=32), -2),
@@ -92,7 +104,7 @@ def test_empty_image_sets_are_a_no_op(lib):
 def test_mfma_entry_point_validates(lib):
     p = C.c_void_p(4096)
     #                              T  r   src  B  H   W   pitch stride kept scaled recon sse
-    assert lib.adct_compress_mfma(3, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
+    assert lib.adct_compress_mfma(6, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 0, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 65, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 10, None, 1, 64, 64, 64, 4096, None, None, None, None,
@@ -115,6 +127,34 @@ def test_other_entry_points_validate(lib):
     assert lib.adct_get_matrix(1, 12, 0, p) == -1
     assert lib.adct_zigzag(7, p) == -1
     assert lib.adct_quant_tables(1, 8, 0, p, p) == -1
+
+
+def test_quality_entry_points_validate(lib):
+    p = C.c_void_p(4096)
+    # psnr: negative count, zero pixels, null and misaligned buffers; count 0 is a no-op
+    assert lib.adct_psnr(-1, 64, p, p, None) == -1
+    assert lib.adct_psnr(3, 0, p, p, None) == -1
+    assert lib.adct_psnr(3, 64, None, p, None) == -1
+    assert lib.adct_psnr(3, 64, C.c_void_p(4100), p, None) == -3
+    assert lib.adct_psnr(0, 64, None, None, None) == 0
+    # moments: transform, n, shape, record alignment, more than 2^32 tiles is refused
+    assert lib.adct_moments(6, 8, p, 0, 1, 8, 8, 8, 64, p, None) == -1
+    assert lib.adct_moments(3, 16, p, 0, 1, 16, 16, 16, 256, p, None) == -1
+    assert lib.adct_moments(1, 12, p, 0, 1, 12, 12, 12, 144, p, None) == -1
+    assert lib.adct_moments(1, 8, p, 0, 1, 12, 8, 8, 96, p, None) == -2
+    assert lib.adct_moments(1, 8, p, 0, 1, 8, 8, 8, 64, C.c_void_p(4100), None) == -3
+    assert lib.adct_moments(1, 8, p, 0, 1, 8, 8, 8, 64, None, None) == -1
+    assert lib.adct_moments(1, 8, p, 0, 0, 8, 8, 8, 64, None, None) == 0
+    assert lib.adct_moments(1, 8, p, 0, 1, 1 << 19, 1 << 19, 1 << 19, 1 << 38, p, None) == -2
+    # coding gains: basis, counts, null pointers
+    assert lib.adct_coding_gain(1, 8, 2, 1, p, p, None) == -1
+    assert lib.adct_coding_gain(1, 8, 1, -1, p, p, None) == -1
+    assert lib.adct_coding_gain(1, 8, 1, 1, None, p, None) == -1
+    assert lib.adct_coding_gain(1, 8, 1, 0, None, None, None) == 0
+    assert lib.adct_coding_gain_ar1(2, 16, 5, 1, p, p, p, None) == -1
+    assert lib.adct_coding_gain_ar1(2, 16, 0, 1, None, p, p, None) == -1
+    assert lib.adct_coding_gain_ar1(2, 16, 0, 4, p, None, None, None) == 0
+    assert lib.adct_coding_gain_ar1(2, 16, 0, 4, C.c_void_p(4098), p, None, None) == -3
 
 
 def test_python_front_end_refuses_host_tensors():
