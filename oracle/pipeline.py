@@ -41,7 +41,7 @@ import math
 
 import numpy as np
 
-from .matrices import (diag_ttt, scale_vector, scaled_inverse, transform_matrix,
+from .matrices import (dct2_matrix, diag_ttt, scale_vector, scaled_inverse, transform_matrix,
                        zigzag, near_orthogonal)
 from .metrics import coding_gain_2d, variance_from_sums
 
@@ -272,3 +272,30 @@ def empirical_coding_gain(img: np.ndarray, kind: int, n: int, basis: str = "cols
     section 5.1."""
     var_c, var_x = coefficient_variances(coefficient_moments(img, kind, n), kind, n)
     return coding_gain_2d(near_orthogonal(kind, n), var_c, var_x, basis)
+
+
+# ----------------------------------------------- the exact DCT (section 5.1)
+def compress_dct(img: np.ndarray, r: int) -> dict:
+    """The still-image experiment with the exact 8-point DCT-II, the reference
+    transform of section 5 (float64): c = C A C^T with the orthonormal C8,
+    the first r zig-zag coefficients kept, A~ = C^T c C, then round, +128
+    and clip (or saturate for int16).  ``scaled`` holds the kept orthonormal
+    coefficients in zig-zag order; ``margin`` is each pixel's distance from
+    the nearest rounding tie (A~ + 1/2 at an integer), which says where a
+    reconstruction in lower precision may round the other way."""
+    n = 8
+    c8 = dct2_matrix(n)
+    a = to_tiles(level_shift(img), n).astype(np.float64)
+    coef = c8 @ a @ c8.T
+    scaled = zigzag_gather(coef, r)
+    masked = np.where(zigzag_mask(n, r), coef, 0.0)
+    x = from_tiles(c8.T @ masked @ c8)
+    y = round_half_away_float(x)
+    frac = np.abs(x) - np.floor(np.abs(x))
+    margin = np.abs(frac - 0.5)
+    if img.dtype == np.uint8:
+        recon = np.clip(y + 128, 0, 255).astype(np.uint8)
+    else:
+        recon = np.clip(y, -32768, 32767).astype(np.int16)
+    e = sse(img, recon)
+    return dict(scaled=scaled, recon=recon, sse=e, psnr=psnr(e, img.size), margin=margin)

@@ -259,3 +259,61 @@ def test_paper_literal_form_is_close_to_separable_form():
         rec = np.clip(P.round_half_away_float(P.from_tiles(cinv @ bl @ c)) + 128, 0, 255)
         p_lit = P.psnr(P.sse(img, rec.astype(np.uint8)), img.size)
         assert abs(p_lit - P.compress(img, kind, 8, 10)["psnr"]) < 0.1
+
+
+# ------------------------------------------------ the exact DCT (section 5)
+def _dct_by_cosine_sums(a):
+    """c_vu = (2/N) k_v k_u sum_ij a_ij cos((2i+1) v pi / 2N) cos((2j+1) u pi / 2N),
+    k_0 = 1/sqrt(2), k = 1 otherwise: the DCT-II written out term by term."""
+    n = a.shape[0]
+    out = np.zeros((n, n))
+    for v in range(n):
+        for u in range(n):
+            kv = 1 / math.sqrt(2) if v == 0 else 1.0
+            ku = 1 / math.sqrt(2) if u == 0 else 1.0
+            acc = 0.0
+            for i in range(n):
+                for j in range(n):
+                    acc += a[i, j] * math.cos((2 * i + 1) * v * math.pi / (2 * n)) * \
+                        math.cos((2 * j + 1) * u * math.pi / (2 * n))
+            out[v, u] = 2.0 / n * kv * ku * acc
+    return out
+
+
+def test_dct_pipeline_against_cosine_sums_and_special_cases():
+    rng = np.random.default_rng(21)
+    img = rng.integers(0, 256, size=(16, 24), dtype=np.uint8)
+    out = P.compress_dct(img, 64)
+    # coefficients: the DCT-II written out term by term
+    a = img.astype(np.float64) - 128
+    for ty in range(2):
+        for tx in range(3):
+            want = _dct_by_cosine_sums(a[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8])
+            got = out["scaled"][ty, tx]
+            want_zz = np.array([want[v, u] for v, u in M.zigzag(8)])
+            assert np.allclose(got, want_zz, rtol=0, atol=1e-9)
+            # orthonormal: energy is preserved (Parseval)
+            assert np.isclose(np.sum(got ** 2), np.sum(a[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8] ** 2))
+    # every coefficient kept: the reconstruction is exact
+    assert np.array_equal(out["recon"], img) and out["sse"] == 0 and math.isinf(out["psnr"])
+    # r = 1: the block mean, rounded half away from zero (skip blocks whose mean is a tie)
+    rec = P.compress_dct(img, 1)["recon"].astype(np.int64)
+    for ty in range(2):
+        for tx in range(3):
+            blk = a[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8]
+            m = blk.mean()
+            if abs(abs(m) - math.floor(abs(m)) - 0.5) < 1e-9:
+                continue
+            want = int(np.sign(m) * math.floor(abs(m) + 0.5)) + 128
+            assert np.all(rec[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8] == want)
+
+
+def test_dct_pipeline_quality_ordering():
+    """Section 5: the exact DCT reconstructs AR(1)-like images better than
+    the approximations at every retention level below 64."""
+    import synth
+    img = synth.ar1_image(64, 64, rho=0.95, seed=2)
+    for r in (1, 6, 10, 28, 45):
+        dct = P.compress_dct(img, r)["psnr"]
+        for kind in M.KINDS:
+            assert dct >= P.compress(img, kind, 8, r)["psnr"] - 1e-9
