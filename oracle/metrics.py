@@ -8,7 +8,15 @@ baseline may use this module.  It shares no code with the HIP library.
   * unified coding gain C_g and the KLT coding gain under the AR(1) model
     R_x[m][n] = rho^|m-n| (section 4.1);
   * additive complexity of a chain of sparse factors (section 4.2, Tables 2
-    and 4).
+    and 4);
+  * the structural similarity index SSIM (Gaussian 11 x 11 window, sigma 1.5,
+    K1 = 0.01, K2 = 0.03, mean over every full window) and the absolute
+    percentage error relative to the exact DCT, the image-quality measures of
+    section 5.1.  The paper cites the SSIM without restating it; the index
+    is taken as its authors define it, without any downsampling.  Pinned by
+    closed forms (identical images, constant images), symmetry and a
+    brute-force window; parity unpinned against the paper's own SSIM values,
+    whose images are not available.
 
 Reading: section 4.1 defines g_k as the k-th row of C^-1.  The textbook
 unified coding gain uses the synthesis basis, i.e. the columns of C^-1.  Both
@@ -131,3 +139,55 @@ def additions_of_factor(m: np.ndarray) -> int:
 def additions_of_chain(factors) -> int:
     """Section 4.2: addition counts (Tables 2 and 4)."""
     return sum(additions_of_factor(f) for f in factors)
+
+
+# ------------------------------------------------ structural similarity (SSIM)
+SSIM_WINDOW = 11          # Gaussian window of the SSIM index, 11 x 11
+SSIM_SIGMA = 1.5          # its standard deviation
+SSIM_K1, SSIM_K2 = 0.01, 0.03
+
+
+def ssim_window() -> np.ndarray:
+    """The normalised 11 x 11 Gaussian weighting window (sigma 1.5) of the
+    SSIM index that section 5.1 cites (Wang et al. 2004)."""
+    r = SSIM_WINDOW // 2
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-(t[:, None] ** 2 + t[None, :] ** 2) / (2.0 * SSIM_SIGMA ** 2))
+    return g / g.sum()
+
+
+def ssim_map(x: np.ndarray, y: np.ndarray, peak: float = 255.0) -> np.ndarray:
+    """SSIM of every full 11 x 11 window of two images (the 'valid' windows,
+    (H - 10) x (W - 10) of them), in float64:
+      SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2))
+    with Gaussian-weighted means, variances and covariance and
+    C1 = (K1 L)^2, C2 = (K2 L)^2.  Section 5.1's quality measure (Wang et
+    al. 2004), evaluated window by window as a weighted sum."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    w = ssim_window()
+    k = SSIM_WINDOW
+    h, wd = x.shape
+    if h < k or wd < k:
+        raise ValueError("images smaller than the SSIM window")
+    c1 = (SSIM_K1 * peak) ** 2
+    c2 = (SSIM_K2 * peak) ** 2
+    from numpy.lib.stride_tricks import sliding_window_view
+    xw = sliding_window_view(x, (k, k))
+    yw = sliding_window_view(y, (k, k))
+    mx = np.einsum("ijab,ab->ij", xw, w)
+    my = np.einsum("ijab,ab->ij", yw, w)
+    sxx = np.einsum("ijab,ab->ij", (xw - mx[..., None, None]) ** 2, w)
+    syy = np.einsum("ijab,ab->ij", (yw - my[..., None, None]) ** 2, w)
+    sxy = np.einsum("ijab,ab->ij", (xw - mx[..., None, None]) * (yw - my[..., None, None]), w)
+    return ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx ** 2 + my ** 2 + c1) * (sxx + syy + c2))
+
+
+def mean_ssim(x: np.ndarray, y: np.ndarray, peak: float = 255.0) -> float:
+    """Mean SSIM over all full windows (section 5.1's SSIM of an image pair)."""
+    return float(np.mean(ssim_map(x, y, peak)))
+
+
+def absolute_percentage_error(value: float, reference: float) -> float:
+    """APE of a measure relative to the exact DCT's (section 5.1), in percent."""
+    return 100.0 * abs(value - reference) / abs(reference)
