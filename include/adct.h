@@ -225,6 +225,27 @@ ADCT_API int adct_moments(int transform, int n, const void* d_src, int dtype, in
 ADCT_API int adct_coding_gain(int transform, int n, int basis, int count,
                               const uint64_t* d_moments, float* d_cg, adct_stream_t stream);
 
+/* adct_compress plus the quality measures of each image in one call: the
+ * fused pipeline (outputs d_kept, d_scaled, d_recon as in adct_compress, each
+ * nullable), then d_psnr[i] (float32 PSNR of image i, section 5.1, nullable)
+ * and d_cg[i] (its measured 2D coding gain, as adct_coding_gain with the
+ * given basis, section 4.1; nullable).  The error energies and moment records
+ * this needs live in the caller's device workspace d_work (8-byte aligned,
+ * work_bytes >= adct_compress_quality_workspace(n, batch, d_cg != NULL));
+ * the call zeroes them itself, and their contents after the call are
+ * unspecified.  ADCT_E_BUDGET when the workspace is too small.  Other
+ * arguments and errors as for adct_compress. */
+ADCT_API int adct_compress_quality(int transform, int n, int r, int qstep, const void* d_src,
+                                   int dtype, int batch, int height, int width, int64_t pitch,
+                                   int64_t image_stride, int32_t* d_kept, float* d_scaled,
+                                   void* d_recon, float* d_psnr, float* d_cg, int basis,
+                                   void* d_work, int64_t work_bytes, adct_stream_t stream);
+
+/* Bytes of the workspace adct_compress_quality needs: 8 * batch * (1 +
+ * (with_coding_gain ? ADCT_MOMENT_WORDS(n) : 0)); a negative status for a bad
+ * n or batch.  Host-side. */
+ADCT_API int64_t adct_compress_quality_workspace(int n, int batch, int with_coding_gain);
+
 /* Coding gain (dB) of C = S' T under the first-order Markov model of section
  * 4.1, R_x[m][n] = rho^|m - n|, for count correlation values d_rho[i] in
  * [0, 1) (device float32): d_cg[i] = -10 / n * sum_k log10(A_k B_k) with

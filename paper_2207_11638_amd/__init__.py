@@ -17,11 +17,12 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import ADCT_I16, ADCT_T1, ADCT_T2, ADCT_U8, AdctError
+from ._lib import (ADCT_DCT, ADCT_HT, ADCT_I16, ADCT_SDCT, ADCT_T1, ADCT_T2, ADCT_U8, ADCT_WHT,
+                   AdctError)
 
-__all__ = ["ADCT_T1", "ADCT_T2", "AdctError", "get_matrix", "zigzag", "scale_vector",
+__all__ = ["ADCT_T1", "ADCT_T2", "ADCT_WHT", "ADCT_SDCT", "ADCT_HT", "ADCT_DCT", "AdctError", "get_matrix", "zigzag", "scale_vector",
            "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path",
-           "psnr", "moments", "coding_gain", "coding_gain_ar1",
+           "psnr", "moments", "coding_gain", "coding_gain_ar1", "compress_quality",
            "BatchPlan", "IMAGE_DESC", "TU_DESC"]
 
 library_path = _lib.LIB_PATH
@@ -240,6 +241,37 @@ def coding_gain(mom, transform: int, n: int, basis: str = "cols", out=None):
     _lib.check(_lib.load().adct_coding_gain(transform, n, _basis_code(basis), mom.shape[0],
                                             _ptr(mom), _ptr(out), _stream_handle(mom.device)))
     return out
+
+
+def compress_quality(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True,
+                     scaled=True, recon=True, coding_gain=True, basis: str = "cols"):
+    """The fused pipeline plus the float32 PSNR and (optionally) the measured
+    coding gain of every image, in one library call with a workspace the
+    binding allocates.  Returns a dict: kept, scaled, recon (or None), psnr
+    float32 [B], coding_gain float32 [B] (or None)."""
+    torch = _torch()
+    _require_device(x)
+    b, h, w, pitch, istride = _image_geometry(x)
+    dev = x.device
+    tiles = (b, h // n, w // n)
+    kept_t = torch.empty(tiles + (r,), dtype=torch.int32, device=dev) if kept else None
+    scaled_t = torch.empty(tiles + (r,), dtype=torch.float32, device=dev) if scaled else None
+    recon_t = (torch.empty_strided(x.size(), x.stride(), dtype=x.dtype, device=dev)
+               if recon else None)
+    psnr_t = torch.empty(b, dtype=torch.float32, device=dev)
+    cg_t = torch.empty(b, dtype=torch.float32, device=dev) if coding_gain else None
+    lib = _lib.load()
+    nbytes = lib.adct_compress_quality_workspace(n, b, int(bool(coding_gain)))
+    if nbytes < 0:
+        _lib.check(int(nbytes))
+    work = torch.empty(max(1, nbytes // 8), dtype=torch.uint64, device=dev)
+    _lib.check(lib.adct_compress_quality(transform, n, r, qstep, _ptr(x), _dtype_code(x), b, h, w,
+                                         pitch, istride, _ptr(kept_t), _ptr(scaled_t),
+                                         _ptr(recon_t), _ptr(psnr_t), _ptr(cg_t),
+                                         _basis_code(basis), _ptr(work), nbytes,
+                                         _stream_handle(dev)))
+    return {"kept": kept_t, "scaled": scaled_t, "recon": recon_t, "psnr": psnr_t,
+            "coding_gain": cg_t}
 
 
 def coding_gain_ar1(rho, transform: int, n: int, basis: str = "cols"):

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(PKG, "libadct.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "adct.h")
 
 ADCT_T1, ADCT_T2 = 1, 2
+ADCT_WHT, ADCT_SDCT, ADCT_HT, ADCT_DCT = 3, 4, 5, 6
 ADCT_U8, ADCT_I16 = 0, 1
 STATUS = {0: "ADCT_OK", -1: "ADCT_E_ARG", -2: "ADCT_E_SHAPE", -3: "ADCT_E_ALIGN",
           -4: "ADCT_E_HIP", -5: "ADCT_E_BUDGET"}
@@ -32,6 +33,9 @@ _SIGNATURES = {
     "adct_compress_mfma": ([_i32, _i32, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
                             _vp], _i32),
     "adct_psnr": ([_i32, _i64, _vp, _vp, _vp], _i32),
+    "adct_compress_quality": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64,
+                               _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i64, _vp], _i32),
+    "adct_compress_quality_workspace": ([_i32, _i32, _i32], _i64),
     "adct_moments": ([_i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp], _i32),
     "adct_coding_gain": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
     "adct_coding_gain_ar1": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp], _i32),

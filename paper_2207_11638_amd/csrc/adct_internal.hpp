@@ -94,6 +94,8 @@ int launch_coding_gain_ar1(int kind, int n, int basis, const float* rho, int cou
                            float* cg_klt, hipStream_t s);
 int launch_psnr(const unsigned long long* sse, int count, int64_t pixels, float* psnr,
                 hipStream_t s);
+// Zero `words` 64-bit words with a fill kernel (no memset node in a graph).
+int launch_fill_zero(unsigned long long* p, int64_t words, hipStream_t s);
 // Fused 8x8 compress (uint8, zonal) on the int8 matrix cores; t = T[v][i] and
 // u = (8 T^-1)[i][v], row-major.
 int launch_n8_mfma(int kind, const PassParams& p, const int8_t* t, const int8_t* u,

@@ -199,6 +199,67 @@ int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stre
   return ok();
 }
 
+// Words of the compress-with-quality workspace: one error energy per image,
+// then one moment record per image when the coding gain is wanted.
+int64_t quality_words(int n, int batch, bool with_cg) {
+  return static_cast<int64_t>(batch) * (1 + (with_cg ? 3 * n * n + 4 : 0));
+}
+
+// adct_compress followed by PSNR and (optionally) the measured coding gain;
+// the error energies and moment records live in `work` (`words` 64-bit
+// words), zeroed here with a fill kernel.
+int compress_quality(const char* what, int transform, int n, int r, int qstep, const void* d_src,
+                     int dtype, int batch, int height, int width, int64_t pitch,
+                     int64_t image_stride, int32_t* d_kept, float* d_scaled, void* d_recon,
+                     float* d_psnr, float* d_cg, int basis, unsigned long long* work,
+                     int64_t words, adct_stream_t stream) {
+  if (int s = check_common(transform, n)) return s;
+  if (int s = check_r_q(n, r, qstep)) return s;
+  if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
+    return fail(ADCT_E_ARG, "%s: bad basis %d", what, basis);
+  PassParams p{};
+  if (int s = check_images(what, n, dtype, d_src, batch, height, width, pitch, image_stride, p.g))
+    return s;
+  if (p.g.batch == 0 || p.g.tiles_x == 0 || p.g.tiles_y == 0) return ok();
+  if (d_src == nullptr) return fail(ADCT_E_ARG, "%s: null source", what);
+  if (d_recon != nullptr && (reinterpret_cast<uintptr_t>(d_recon) %
+                             std::min<int64_t>(16, static_cast<int64_t>(n) * pixel_bytes(dtype))))
+    return fail(ADCT_E_ALIGN, "%s: misaligned reconstruction buffer", what);
+  if ((reinterpret_cast<uintptr_t>(d_kept) % 4) || (reinterpret_cast<uintptr_t>(d_scaled) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_psnr) % 4) || (reinterpret_cast<uintptr_t>(d_cg) % 4))
+    return fail(ADCT_E_ALIGN, "%s: misaligned output buffer", what);
+  const int64_t need = quality_words(n, batch, d_cg != nullptr);
+  if (words < need)
+    return fail(ADCT_E_BUDGET, "%s: the workspace holds %lld words, %lld needed", what,
+                (long long)words, (long long)need);
+  if (static_cast<int64_t>(p.g.tiles_x) * p.g.tiles_y >= (int64_t(1) << 32))
+    return fail(ADCT_E_SHAPE, "%s: more than 2^32 tiles per image", what);
+  TableSet ts;
+  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  int e = launch_fill_zero(work, need, st);
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  p.t = ts.t;
+  p.src = d_src;
+  p.dst = d_recon;
+  p.cout = d_kept;
+  p.scaled = d_scaled;
+  p.sse = work;
+  p.r = r;
+  p.qstep = qstep;
+  if (int s = launch(Mode::Compress, transform, n, dtype, p, stream)) return s;
+  const int64_t pixels = static_cast<int64_t>(height) * width;
+  if (d_psnr != nullptr) e = launch_psnr(work, batch, pixels, d_psnr, st);
+  if (e == hipSuccess && d_cg != nullptr) {
+    e = launch_moments(transform, n, dtype, d_src, p.g, work + batch, st);
+    if (e == hipSuccess) e = launch_coding_gain(transform, n, basis, work + batch, batch, d_cg, st);
+  }
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
 }  // namespace
 
 int set_error(int status, const char* msg) {
@@ -393,6 +454,25 @@ ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int bat
   if (e != hipSuccess)
     return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();
+}
+
+ADCT_API int64_t adct_compress_quality_workspace(int n, int batch, int with_coding_gain) {
+  if (!valid_n(n) || batch < 0) return fail(ADCT_E_ARG, "quality workspace: bad n or batch");
+  return 8 * quality_words(n, batch, with_coding_gain != 0);
+}
+
+ADCT_API int adct_compress_quality(int transform, int n, int r, int qstep, const void* d_src,
+                                   int dtype, int batch, int height, int width, int64_t pitch,
+                                   int64_t image_stride, int32_t* d_kept, float* d_scaled,
+                                   void* d_recon, float* d_psnr, float* d_cg, int basis,
+                                   void* d_work, int64_t work_bytes, adct_stream_t stream) {
+  if (d_work == nullptr && batch > 0) return fail(ADCT_E_ARG, "compress_quality: null workspace");
+  if (reinterpret_cast<uintptr_t>(d_work) % 8)
+    return fail(ADCT_E_ALIGN, "compress_quality: misaligned workspace");
+  return compress_quality("compress_quality", transform, n, r, qstep, d_src, dtype, batch, height,
+                          width, pitch, image_stride, d_kept, d_scaled, d_recon, d_psnr, d_cg,
+                          basis, static_cast<unsigned long long*>(d_work),
+                          work_bytes < 0 ? 0 : work_bytes / 8, stream);
 }
 
 ADCT_API int adct_psnr(int count, int64_t pixels, const uint64_t* d_sse, float* d_psnr,

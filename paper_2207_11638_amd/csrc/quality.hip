@@ -21,6 +21,8 @@
 // the image's tile groups; one set of 64-bit atomics per workgroup adds them
 // to the image's record.  Squares are split into their low and high 32-bit
 // halves, each summed in 64 bits, so every sum is exact for any int16 input.
+#include <algorithm>
+
 #include "jam_group.hpp"
 
 namespace adct {
@@ -379,6 +381,13 @@ __global__ __launch_bounds__(64) void coding_gain_ar1_kernel(const float* rho, i
   }
 }
 
+// -------------------------------------------------------------- workspace
+__global__ void fill_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0ull;
+}
+
 // -------------------------------------------------------------------- PSNR
 __global__ void psnr_plain_kernel(const unsigned long long* sse, int count, float npix, float* psnr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,6 +478,13 @@ int launch_coding_gain_ar1(int kind, int n, int basis, const float* rho, int cou
     case KIND_SIGN: return launch_ar1_typed<KIND_SIGN>(n, rho, count, basis, cg, cg_klt, s);
     default: return launch_ar1_typed<KIND_ROUND>(n, rho, count, basis, cg, cg_klt, s);
   }
+  return hipGetLastError();
+}
+
+int launch_fill_zero(unsigned long long* p, int64_t words, hipStream_t s) {
+  if (words <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((words + 255) / 256, 4096);
+  fill_zero_u64<<<static_cast<int>(blocks), 256, 0, s>>>(p, words);
   return hipGetLastError();
 }
 

@@ -170,6 +170,53 @@ def test_quality_calls_reject_bad_arguments():
     with pytest.raises(ValueError):
         adct.coding_gain_ar1(rho, 1, 8, "diagonal")
     with pytest.raises(adct.AdctError):
-        adct.coding_gain_ar1(rho, 3, 8)
+        adct.coding_gain_ar1(rho, 6, 8)
     with pytest.raises(adct.AdctError):
         adct.moments(to_dev(np.zeros((12, 16), np.uint8)), 1, 8)   # 12 rows: not a multiple of 8
+
+
+@pytest.mark.parametrize("kind,n,dtype,r,q", [(1, 8, "u8", 10, 0), (2, 16, "u8", 28, 0),
+                                              (2, 32, "i16", 1024, 16), (3, 8, "u8", 6, 0)])
+def test_compress_quality_matches_oracle(kind, n, dtype, r, q):
+    h, w = SHAPES[n]
+    if dtype == "u8":
+        imgs = [synth.ar1_image(h, w, rho=0.9, seed=900 + i) for i in range(3)]
+    else:
+        imgs = [synth.laplace_residual(h, w, seed=910 + i) for i in range(3)]
+    x = to_dev(np.stack(imgs))
+    out = adct.compress_quality(x, kind, n, r, q)
+    kept, rec = host(out["kept"]), host(out["recon"])
+    ps, cg = host(out["psnr"]), host(out["coding_gain"])
+    for i, im in enumerate(imgs):
+        want = P.compress(im, kind, n, r, q)
+        assert np.array_equal(kept[i], want["kept"])
+        assert np.array_equal(rec[i], want["recon"])
+        assert close(ps[i], want["psnr"]), (ps[i], want["psnr"])
+        want_cg = P.empirical_coding_gain(im, kind, n, "cols")
+        assert close(cg[i], want_cg), (cg[i], want_cg)
+    # the same outputs as the separate calls
+    sep = adct.compress(x, kind, n, r, q)
+    assert np.array_equal(host(sep["kept"]), kept)
+    assert np.array_equal(host(adct.psnr(sep["sse"], h * w)), ps)
+
+
+def test_compress_quality_workspace_checks():
+    from paper_2207_11638_amd import _lib
+    import ctypes as C
+    lib = _lib.load()
+    x = to_dev(synth.ar1_image(16, 64, seed=1))
+    need = lib.adct_compress_quality_workspace(8, 1, 1)
+    assert need == 8 * (1 + 3 * 64 + 4)
+    work = torch.zeros(need // 8, dtype=torch.uint64, device=DEV)
+    psnr = torch.zeros(1, dtype=torch.float32, device=DEV)
+    cg = torch.zeros(1, dtype=torch.float32, device=DEV)
+    args = [1, 8, 10, 0, C.c_void_p(x.data_ptr()), 0, 1, 16, 64, 64, 16 * 64, None, None, None,
+            C.c_void_p(psnr.data_ptr()), C.c_void_p(cg.data_ptr()), 1,
+            C.c_void_p(work.data_ptr())]
+    assert lib.adct_compress_quality(*args, need - 8, None) == -5      # too small
+    assert lib.adct_compress_quality(*args[:15], None, 1, C.c_void_p(work.data_ptr()), 8,
+                                     None) == 0                        # PSNR only: one word
+    assert lib.adct_compress_quality(*args, need, None) == 0
+    torch.cuda.synchronize()
+    want = P.compress(host(x), 1, 8, 10)
+    assert close(host(psnr)[0], want["psnr"])
