@@ -241,6 +241,24 @@ ADCT_API int adct_compress_quality(int transform, int n, int r, int qstep, const
                                    void* d_recon, float* d_psnr, float* d_cg, int basis,
                                    void* d_work, int64_t work_bytes, adct_stream_t stream);
 
+/* adct_compress_quality for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments without the workspace, the same outputs.
+ * The error energies and moment records go to a fixed scratch array of
+ * 2^19 64-bit words (4 MiB) that the library holds on every GPU it runs on
+ * until the process ends, so batch * (1 + (d_cg != NULL ? ADCT_MOMENT_WORDS(n)
+ * : 0)) must not exceed 524288 (ADCT_E_BUDGET otherwise, before any GPU
+ * work).  The call allocates and frees no device memory.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and their results are undefined.  Call it with the
+ * device of `stream` current. */
+ADCT_API int adct_compress_quality_noalloc(int transform, int n, int r, int qstep,
+                                           const void* d_src, int dtype, int batch, int height,
+                                           int width, int64_t pitch, int64_t image_stride,
+                                           int32_t* d_kept, float* d_scaled, void* d_recon,
+                                           float* d_psnr, float* d_cg, int basis,
+                                           adct_stream_t stream);
+
 /* Bytes of the workspace adct_compress_quality needs: 8 * batch * (1 +
  * (with_coding_gain ? ADCT_MOMENT_WORDS(n) : 0)); a negative status for a bad
  * n or batch.  Host-side. */

@@ -36,6 +36,8 @@ _SIGNATURES = {
     "adct_compress_quality": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64,
                                _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i64, _vp], _i32),
     "adct_compress_quality_workspace": ([_i32, _i32, _i32], _i64),
+    "adct_compress_quality_noalloc": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64,
+                                       _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
     "adct_moments": ([_i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp], _i32),
     "adct_coding_gain": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
     "adct_coding_gain_ar1": ([_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp], _i32),

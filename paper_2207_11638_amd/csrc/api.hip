@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -199,6 +200,36 @@ int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stre
   return ok();
 }
 
+// Scratch of adct_compress_quality_noalloc: the error energies and moment
+// records of one call, in a fixed array of device memory that every GPU the
+// library runs on holds until the process ends (4 MiB).  Host code uses the
+// per-device address from hipGetSymbolAddress, never the array's name.
+constexpr int64_t kScratchWords = int64_t(1) << 19;
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device, looked up once per
+// device (with that device current).
+int static_scratch(unsigned long long** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ADCT_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ADCT_E_HIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(ADCT_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned long long*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return ADCT_OK;
+}
+
 // Words of the compress-with-quality workspace: one error energy per image,
 // then one moment record per image when the coding gain is wanted.
 int64_t quality_words(int n, int batch, bool with_cg) {
@@ -208,11 +239,13 @@ int64_t quality_words(int n, int batch, bool with_cg) {
 // adct_compress followed by PSNR and (optionally) the measured coding gain;
 // the error energies and moment records live in `work` (`words` 64-bit
 // words), zeroed here with a fill kernel.
+int static_scratch(unsigned long long** out);
+
 int compress_quality(const char* what, int transform, int n, int r, int qstep, const void* d_src,
                      int dtype, int batch, int height, int width, int64_t pitch,
                      int64_t image_stride, int32_t* d_kept, float* d_scaled, void* d_recon,
                      float* d_psnr, float* d_cg, int basis, unsigned long long* work,
-                     int64_t words, adct_stream_t stream) {
+                     int64_t words, bool use_static_scratch, adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
   if (int s = check_r_q(n, r, qstep)) return s;
   if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
@@ -236,6 +269,8 @@ int compress_quality(const char* what, int transform, int n, int r, int qstep, c
     return fail(ADCT_E_SHAPE, "%s: more than 2^32 tiles per image", what);
   TableSet ts;
   if (int s = build_tables(transform, n, qstep, ts)) return s;
+  if (use_static_scratch)
+    if (int s = static_scratch(&work)) return s;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   int e = launch_fill_zero(work, need, st);
   if (e != hipSuccess)
@@ -472,7 +507,18 @@ ADCT_API int adct_compress_quality(int transform, int n, int r, int qstep, const
   return compress_quality("compress_quality", transform, n, r, qstep, d_src, dtype, batch, height,
                           width, pitch, image_stride, d_kept, d_scaled, d_recon, d_psnr, d_cg,
                           basis, static_cast<unsigned long long*>(d_work),
-                          work_bytes < 0 ? 0 : work_bytes / 8, stream);
+                          work_bytes < 0 ? 0 : work_bytes / 8, false, stream);
+}
+
+ADCT_API int adct_compress_quality_noalloc(int transform, int n, int r, int qstep,
+                                           const void* d_src, int dtype, int batch, int height,
+                                           int width, int64_t pitch, int64_t image_stride,
+                                           int32_t* d_kept, float* d_scaled, void* d_recon,
+                                           float* d_psnr, float* d_cg, int basis,
+                                           adct_stream_t stream) {
+  return compress_quality("compress_quality_noalloc", transform, n, r, qstep, d_src, dtype, batch,
+                          height, width, pitch, image_stride, d_kept, d_scaled, d_recon, d_psnr,
+                          d_cg, basis, nullptr, kScratchWords, true, stream);
 }
 
 ADCT_API int adct_psnr(int count, int64_t pixels, const uint64_t* d_sse, float* d_psnr,
