@@ -49,7 +49,7 @@ SDCT = 4
 HT = 5
 KINDS = (SIGN, ROUND)
 COMPARISON_KINDS = (WHT, SDCT, HT)
-SIZES = (8, 16, 32)
+SIZES = (8, 16, 32, 64)   # block lengths: the recursion of section 6.1 to its 64-point level
 
 
 # ---------------------------------------------------------------- section 2

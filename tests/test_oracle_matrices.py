@@ -203,14 +203,14 @@ def test_m_per_literal_block_reading_is_the_interleave():
 
 
 @pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", (16, 32))
+@pytest.mark.parametrize("n", (16, 32, 64))
 def test_jam_recursion_equals_factorized_form(kind, n):
     p, m1, m2, m3, m4, b = M.jam_factors(kind, n)
     assert np.array_equal(p @ m1 @ m2 @ m3 @ m4 @ b, M.transform_matrix(kind, n))
 
 
 @pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", (16, 32))
+@pytest.mark.parametrize("n", (16, 32, 64))
 def test_jam_inverse_factorization(kind, n):
     # T_N^-1 = (4/N) Bcheck^T M4^-1 M3^-1 M2^-1 M1^T Pcheck^T (section 6.1)
     p, m1, m2, m3, m4, b = M.jam_factors(kind, n)
@@ -223,7 +223,7 @@ def test_jam_inverse_factorization(kind, n):
 
 
 @pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", (16, 32))
+@pytest.mark.parametrize("n", (16, 32, 64))
 def test_jam_even_rows_mirror_half_transform(kind, n):
     t = M.transform_matrix(kind, n)
     half = M.transform_matrix(kind, n // 2)
@@ -233,7 +233,7 @@ def test_jam_even_rows_mirror_half_transform(kind, n):
 
 
 @pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", (16, 32))
+@pytest.mark.parametrize("n", (16, 32, 64))
 def test_jam_odd_rows_act_on_the_difference_vector(kind, n):
     # odd rows apply T_{N/2} to w = Ibar x_top - x_bottom
     t = M.transform_matrix(kind, n)
@@ -249,7 +249,7 @@ def test_zigzag_matches_jpeg_scan():
     assert [v * 8 + u for v, u in M.zigzag(8)] == jpeg.tolist()
 
 
-@pytest.mark.parametrize("n", (8, 16, 32))
+@pytest.mark.parametrize("n", (8, 16, 32, 64))
 def test_zigzag_is_a_permutation_by_antidiagonals(n):
     zz = M.zigzag(n)
     assert sorted(zz) == [(v, u) for v in range(n) for u in range(n)]
@@ -261,7 +261,7 @@ def test_zigzag_is_a_permutation_by_antidiagonals(n):
             assert abs(v1 - v0) == 1 and abs(u1 - u0) == 1
 
 
-@pytest.mark.parametrize("n", (8, 16, 32))
+@pytest.mark.parametrize("n", (8, 16, 32, 64))
 def test_zigzag_prefix_keeps_a_prefix_of_every_column(n):
     # for every r, the rows kept in column u by the first r scan positions are
     # 0 .. c_u - 1 (the JAM kernels mask each column by such a count)

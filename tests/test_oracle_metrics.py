@@ -38,7 +38,7 @@ def test_deviation_closed_forms():
 
 
 @pytest.mark.parametrize("kind", M.KINDS)
-@pytest.mark.parametrize("n", (16, 32))
+@pytest.mark.parametrize("n", (16, 32, 64))
 def test_jam_keeps_deviation(kind, n):
     # the JAM recursion keeps delta: it maps T T^T to a direct sum of copies
     t8 = M.transform_matrix(kind, 8)
