@@ -265,13 +265,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("c0", "c1", "c2", "c3", "c4", "plain"), default="c1",
+    ap.add_argument("--workload", choices=("c0", "c1", "c2", "c3", "c4", "plain", "ceiling",
+                                           "sweep"),
+                    default="c1",
                     help="c0: latency of one 512^2 image; "
                          "c1: the 1024 x 2048^2 sweep (default; the line also carries the "
                          "ragged batch against per-image launches and the serving latency); "
                          "c2: the int16 residual frames with 16/32-point transforms and "
                          "quantisation; c3: the ragged batch alone; c4: the serving loop alone; "
-                         "plain: one fused configuration (--n, --transform, --r, --qstep)")
+                         "plain: one fused configuration (--n, --transform, --r, --qstep); "
+                         "ceiling: the HBM read/write/copy ceilings of plain 16-byte kernels; "
+                         "sweep: the transform assessment of section 4.1 (error energy, "
+                         "deviation from diagonality, coding gain minus the KLT's over rho)")
     ap.add_argument("--engine", choices=("butterfly", "mfma"), default="butterfly",
                     help="c1/plain: N=8 uint8 zonal passes on the butterflies or on the int8 "
                          "matrix cores")
@@ -329,6 +334,10 @@ def main():
         print(json.dumps(c4_line(args, data, gpu_c4(args, data, sweep=True))), flush=True)
     elif args.workload == "plain":
         run_plain(args)
+    elif args.workload == "ceiling":
+        run_ceiling(args)
+    elif args.workload == "sweep":
+        run_sweep(args)
     else:
         run_c1(args)
 
@@ -549,6 +558,112 @@ def gpu_c1(args, imgs, cpu):
         "parity_sample": check,
         "cpu_baseline": cpu,
     }
+
+
+# ------------------------------------------------- transform assessment sweep
+def run_sweep(args):
+    """Section 4.1's assessment of every transform the library offers: the
+    total error energy and the deviation from diagonality (host, float64) and
+    the coding gain minus the KLT's under the AR(1) model for rho in [0, 1)
+    (one GPU launch per transform over the whole rho grid, float32, columns
+    basis).  A sample of the grid is checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2207_11638_amd as adct
+    dev = gpu_device()
+    rhos = np.concatenate([np.arange(0, 100) / 100.0, [0.995, 0.999]]).astype(np.float32)
+    d_rho = torch.from_numpy(rhos).to(dev)
+    combos = [(k, n) for k in (1, 2) for n in (8, 16, 32, 64)] + [(k, 8) for k in (3, 4, 5)]
+    names = {1: "T1", 2: "T2", 3: "WHT", 4: "SDCT", 5: "HT"}
+    rows, cg_all, klt_all = [], {}, {}
+    t0 = time.perf_counter()
+    for k, n in combos:
+        cg, klt = adct.coding_gain_ar1(d_rho, k, n, "cols")
+        cg_all[(k, n)], klt_all[(k, n)] = cg, klt
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    for k, n in combos:
+        eps, delta = adct.transform_measures(k, n)
+        diff = (cg_all[(k, n)] - klt_all[(k, n)]).cpu().numpy().astype(np.float64)
+        pick = {f"{r:.3f}": round(float(diff[i]), 4) for i, r in enumerate(rhos)
+                if round(float(r), 3) in (0.5, 0.9, 0.95, 0.99)}
+        rows.append({"transform": names[k], "n": n, "eps": round(eps, 4), "delta": round(delta, 4),
+                     "cg_minus_klt_db": pick})
+        log(f"{names[k]} N={n}: eps {eps:.4f}, delta {delta:.4f}, C_g - C_g(KLT) {pick}")
+    check = None
+    if not args.no_check:
+        from oracle import matrices as M
+        from oracle import metrics as Q
+        bad = 0
+        for k, n in combos:
+            c = M.near_orthogonal(k, n)
+            cg = cg_all[(k, n)].cpu().numpy()
+            kl = klt_all[(k, n)].cpu().numpy()
+            for i in range(0, len(rhos), 7):
+                r = float(rhos[i])
+                for got, want in ((cg[i], Q.coding_gain(c, r, "cols")),
+                                  (kl[i], Q.klt_coding_gain(n, r))):
+                    bad += int(abs(float(got) - want) > 1e-5 * max(abs(want), 1.0))
+        check = "ok" if bad == 0 else f"{bad} mismatches"
+        log(f"sampled parity vs oracle (every 7th rho, every transform): {check}")
+    print(json.dumps({"workload": "transform assessment of section 4.1 over rho in [0, 1)",
+                      "rho_values": len(rhos), "gpu_seconds": round(gpu_s, 4),
+                      "basis": "columns of C^-1", "transforms": rows,
+                      "parity_sample": check}), flush=True)
+
+
+# ------------------------------------------------------------ HBM ceilings
+CEILING_BYTES = 4 << 30
+
+
+def run_ceiling(args):
+    """Read-only, write-only and copy streams of 4 GiB through the library's
+    plain 16-byte non-temporal kernels (adct_stream_ceiling), over a sweep of
+    grid sizes and loads in flight; each point timed with HIP events on the
+    launch stream over --steps launches after --warmup.  Prints the best rate
+    of each pattern (bytes moved: read, written, or both for the copy)."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2207_11638_amd import _lib
+    lib = _lib.load()
+    dev = gpu_device()
+    src = torch.zeros(CEILING_BYTES, dtype=torch.uint8, device=dev)
+    dst = torch.empty(CEILING_BYTES, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    results = {}
+    for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+        best = None
+        for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+            for unroll in ((1,) if pattern == 1 else (1, 2, 4, 8)):
+                def go():
+                    _lib.check(lib.adct_stream_ceiling(pattern, C.c_void_p(dst.data_ptr()),
+                                                       C.c_void_p(src.data_ptr()), CEILING_BYTES,
+                                                       blocks, unroll, sp))
+                for _ in range(max(1, args.warmup)):
+                    go()
+                a = torch.cuda.Event(enable_timing=True)
+                z = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(args.steps):
+                    go()
+                z.record(stream)
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(z) / args.steps
+                gbs = moved * CEILING_BYTES / ms / 1e6
+                log(f"{name}: {blocks} workgroups, {unroll} in flight: {ms:.3f} ms, {gbs:.0f} GB/s")
+                if best is None or gbs > best["GBps"]:
+                    best = {"GBps": round(gbs, 1), "ms": round(ms, 4), "workgroups": blocks,
+                            "unroll": unroll}
+        results[name] = best
+    print(json.dumps({"workload": "HBM streaming ceilings, 4 GiB per buffer, 16-byte "
+                                  "non-temporal accesses", "peak_GBps": HBM_PEAK_GBS,
+                      "ceilings": results,
+                      "fraction_of_peak": {k: round(v["GBps"] / HBM_PEAK_GBS, 4)
+                                           for k, v in results.items()}}), flush=True)
 
 
 # ---------------------------------------------------------------- one config

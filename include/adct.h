@@ -23,7 +23,11 @@
  *              2) and exact integer inverses N T^-1, so every device call
  *              below computes them with the same kernels (the ragged-batch
  *              and serving calls take ADCT_T1 and ADCT_T2 only).
- *   n          block length N in {8, 16, 32}.
+ *   n          block length N in {8, 16, 32, 64}.  The 64-point level of the
+ *              recursion of section 6.1 takes ADCT_T1 / ADCT_T2, 8-bit images
+ *              and zonal retention only (ADCT_E_ARG otherwise): its int32
+ *              intermediates are exact for 8-bit input but not over the
+ *              whole int16 range.
  *   dtype      ADCT_U8: 8-bit grey levels, shifted by -128 before the
  *              transform and reconstructed as round(.) + 128 clipped to
  *              [0, 255].  ADCT_I16: signed 16-bit prediction residuals, not
@@ -66,6 +70,10 @@ extern "C" {
 #define ADCT_WHT 3   /* Walsh-Hadamard, rows in sequency order  */
 #define ADCT_SDCT 4  /* signed DCT, sign(C8)                    */
 #define ADCT_HT 5    /* Hadamard, Sylvester's natural row order */
+/* The exact DCT-II (section 2), the reference of section 5, n = 8, in float32:
+ * adct_compress (zonal, d_kept NULL) and adct_compress_quality (no coding
+ * gain) only; d_scaled receives its orthonormal coefficients. */
+#define ADCT_DCT 6
 
 #define ADCT_U8 0
 #define ADCT_I16 1
@@ -97,6 +105,13 @@ ADCT_API const char* adct_last_error(void);
  * unit vectors.  inverse = 1: U_N = N * T_N^-1 (eqs. 6/7 and the inverse
  * factorization of section 6.1), from the inverse butterfly.  */
 ADCT_API int adct_get_matrix(int transform, int n, int inverse, int32_t* host_out);
+
+/* Section 4.1's assessment measures of the transform (host-side, float64):
+ * *eps = pi ||C_N - S' T_N||_F^2, the total error energy against the
+ * orthonormal DCT-II C_N (Table 1), and *delta = 1 - ||diag(M)||^2 / ||M||_F^2
+ * for M = T_N T_N^T, the deviation from diagonality (section 3.1).  Either
+ * pointer may be NULL.  Both are 0 for ADCT_DCT. */
+ADCT_API int adct_transform_measures(int transform, int n, double* eps, double* delta);
 
 /* The zig-zag scan of section 5.1 (the JPEG rule, generalised to n x n by
  * anti-diagonals): host_out[k] = v * n + u of the k-th scanned coefficient
@@ -188,6 +203,24 @@ ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int bat
 /* uint64 words of one moment record of block length n. */
 #define ADCT_MOMENT_WORDS(n) (3 * (n) * (n) + 4)
 
+/* SSIM of section 5.1 (the index of Wang et al., which the paper cites):
+ * d_ssim[i] (float32) is the mean over every full 11 x 11 window of image i
+ * of (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
+ * with Gaussian-weighted (sigma 1.5) means, variances and covariance of the
+ * 8-bit images d_x and d_y (same geometry: batch images of height x width
+ * >= 11 x 11, row pitch and image stride in bytes), C1 = (0.01 * 255)^2,
+ * C2 = (0.03 * 255)^2.  d_work: batch float64 accumulators of caller-owned
+ * device memory, 8-byte aligned, zeroed by the call. */
+ADCT_API int adct_ssim(const void* d_x, const void* d_y, int batch, int height, int width,
+                       int64_t pitch, int64_t image_stride, double* d_work, float* d_ssim,
+                       adct_stream_t stream);
+
+/* Absolute percentage error of section 5.1: d_ape[i] = 100 |d_value[i] -
+ * d_reference[i]| / |d_reference[i]| (float32 device arrays of count entries;
+ * the reference is the exact DCT's measure for the same image). */
+ADCT_API int adct_ape(int count, const float* d_value, const float* d_reference, float* d_ape,
+                      adct_stream_t stream);
+
 /* PSNR of section 5.1 from error energies: d_psnr[i] = 10 log10(255^2 *
  * pixels / d_sse[i]) in float32, +inf where d_sse[i] = 0 (device arrays of
  * count entries; pixels >= 1 is the pixel count of every image).  count = 0
@@ -274,6 +307,19 @@ ADCT_API int64_t adct_compress_quality_workspace(int n, int batch, int with_codi
 ADCT_API int adct_coding_gain_ar1(int transform, int n, int basis, int count,
                                   const float* d_rho, float* d_cg, float* d_cg_klt,
                                   adct_stream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Measurement aid (no operation of the paper): the streaming ceiling of the
+ * HBM that the fused kernels' bandwidth is compared with.  pattern 0 reads
+ * `bytes` from d_src (d_dst receives at most one word, only for a pattern no
+ * zero-filled input produces; pass a zero-filled d_src), 1 writes `bytes` of
+ * zeros to d_dst, 2 copies `bytes` from d_src to d_dst; 16-byte non-temporal
+ * accesses, `blocks` workgroups of 256 threads in grid-stride order with
+ * `unroll` (1, 2, 4 or 8) independent loads in flight per thread.  bytes a
+ * multiple of 16, buffers 16-byte aligned.
+ * ---------------------------------------------------------------------- */
+ADCT_API int adct_stream_ceiling(int pattern, void* d_dst, const void* d_src, int64_t bytes,
+                                 int blocks, int unroll, adct_stream_t stream);
 
 /* ----------------------------------------------------------------------
  * Ragged batches: many images of different sizes, each partitioned into

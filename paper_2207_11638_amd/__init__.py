@@ -21,8 +21,8 @@ from ._lib import (ADCT_DCT, ADCT_HT, ADCT_I16, ADCT_SDCT, ADCT_T1, ADCT_T2, ADC
                    AdctError)
 
 __all__ = ["ADCT_T1", "ADCT_T2", "ADCT_WHT", "ADCT_SDCT", "ADCT_HT", "ADCT_DCT", "AdctError", "get_matrix", "zigzag", "scale_vector",
-           "quant_tables", "fwd2d", "inv2d", "compress", "decompress", "library_path",
-           "psnr", "moments", "coding_gain", "coding_gain_ar1", "compress_quality",
+           "quant_tables", "transform_measures", "fwd2d", "inv2d", "compress", "decompress", "library_path",
+           "psnr", "moments", "coding_gain", "coding_gain_ar1", "compress_quality", "ssim", "ape",
            "BatchPlan", "IMAGE_DESC", "TU_DESC"]
 
 library_path = _lib.LIB_PATH
@@ -46,6 +46,15 @@ def scale_vector(transform: int, n: int) -> np.ndarray:
     out = np.zeros(n, dtype=np.float64)
     _lib.check(_lib.load().adct_scale_vector(transform, n, out.ctypes.data))
     return out
+
+
+def transform_measures(transform: int, n: int):
+    """(total error energy against the DCT, deviation from diagonality of
+    T T^T) of the library's transform (section 4.1, Table 1)."""
+    eps = C.c_double()
+    delta = C.c_double()
+    _lib.check(_lib.load().adct_transform_measures(transform, n, C.byref(eps), C.byref(delta)))
+    return eps.value, delta.value
 
 
 def quant_tables(transform: int, n: int, qstep: int):
@@ -132,7 +141,9 @@ def compress(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True, sc
     False (skip) or a preallocated tensor.  Returns a dict of the produced
     tensors: kept int32 [B, H/n, W/n, r], scaled float32 [B, H/n, W/n, r],
     recon like x, sse uint64 [B] (accumulated into when passed in).
-    engine="mfma" runs the int8 matrix-core form (n = 8, uint8, qstep = 0)."""
+    engine="mfma" runs the int8 matrix-core form (n = 8, uint8, qstep = 0).
+    The exact DCT (ADCT_DCT) has no integer coefficients: kept defaults to
+    False and scaled holds its orthonormal coefficients."""
     if engine not in ("butterfly", "mfma"):
         raise ValueError(f"unknown engine {engine!r}")
     torch = _torch()
@@ -149,6 +160,8 @@ def compress(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=True, sc
         _require_device(v)
         return v
 
+    if transform == ADCT_DCT and kept is True:
+        kept = False
     kept_t = pick(kept, lambda: torch.empty(tiles + (r,), dtype=torch.int32, device=dev))
     scaled_t = pick(scaled, lambda: torch.empty(tiles + (r,), dtype=torch.float32, device=dev))
     recon_t = pick(recon, lambda: torch.empty_strided(x.size(), x.stride(), dtype=x.dtype,
@@ -213,6 +226,38 @@ def psnr(sse, pixels: int, out=None):
     return out
 
 
+def ssim(x, y):
+    """float32 mean SSIM (11 x 11 Gaussian windows) of every image pair of two
+    uint8 tensors of one geometry ([B, H, W] or [H, W])."""
+    torch = _torch()
+    _require_device(x, y)
+    if x.dtype != torch.uint8 or y.dtype != torch.uint8:
+        raise TypeError("SSIM takes uint8 images")
+    b, h, w, pitch, istride = _image_geometry(x)
+    if _image_geometry(y) != (b, h, w, pitch, istride):
+        raise ValueError("x and y must have the same geometry")
+    work = torch.empty(b, dtype=torch.float64, device=x.device)
+    out = torch.empty(b, dtype=torch.float32, device=x.device)
+    _lib.check(_lib.load().adct_ssim(_ptr(x), _ptr(y), b, h, w, pitch, istride, _ptr(work),
+                                     _ptr(out), _stream_handle(x.device)))
+    return out
+
+
+def ape(value, reference):
+    """float32 absolute percentage error of ``value`` against ``reference``."""
+    torch = _torch()
+    _require_device(value, reference)
+    for t in (value, reference):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("APE takes contiguous float32 tensors")
+    if value.numel() != reference.numel():
+        raise ValueError("value and reference differ in size")
+    out = torch.empty_like(value)
+    _lib.check(_lib.load().adct_ape(value.numel(), _ptr(value), _ptr(reference), _ptr(out),
+                                    _stream_handle(value.device)))
+    return out
+
+
 def moments(x, transform: int, n: int, out=None):
     """Coefficient and pixel moments of every image: uint64 [B, 3 n^2 + 4]
     (layout of adct_moments), accumulated into ``out`` when it is given."""
@@ -254,6 +299,8 @@ def compress_quality(x, transform: int, n: int, r: int, qstep: int = 0, *, kept=
     b, h, w, pitch, istride = _image_geometry(x)
     dev = x.device
     tiles = (b, h // n, w // n)
+    if transform == ADCT_DCT:   # no integer coefficients, no moments
+        kept = coding_gain = False
     kept_t = torch.empty(tiles + (r,), dtype=torch.int32, device=dev) if kept else None
     scaled_t = torch.empty(tiles + (r,), dtype=torch.float32, device=dev) if scaled else None
     recon_t = (torch.empty_strided(x.size(), x.stride(), dtype=x.dtype, device=dev)

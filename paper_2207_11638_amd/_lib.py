@@ -21,6 +21,7 @@ _SIGNATURES = {
     "adct_last_error": ([], C.c_char_p),
     "adct_get_matrix": ([_i32, _i32, _i32, _vp], _i32),
     "adct_zigzag": ([_i32, _vp], _i32),
+    "adct_transform_measures": ([_i32, _i32, _vp, _vp], _i32),
     "adct_scale_vector": ([_i32, _i32, _vp], _i32),
     "adct_quant_tables": ([_i32, _i32, _i32, _vp, _vp], _i32),
     "adct_fwd2d": ([_i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64, _vp, _vp], _i32),
@@ -33,6 +34,9 @@ _SIGNATURES = {
     "adct_compress_mfma": ([_i32, _i32, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
                             _vp], _i32),
     "adct_psnr": ([_i32, _i64, _vp, _vp, _vp], _i32),
+    "adct_stream_ceiling": ([_i32, _vp, _vp, _i64, _i32, _i32, _vp], _i32),
+    "adct_ssim": ([_vp, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp], _i32),
+    "adct_ape": ([_i32, _vp, _vp, _vp, _vp], _i32),
     "adct_compress_quality": ([_i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _i64, _i64,
                                _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i64, _vp], _i32),
     "adct_compress_quality_workspace": ([_i32, _i32, _i32], _i64),

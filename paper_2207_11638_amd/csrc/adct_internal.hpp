@@ -27,7 +27,7 @@ struct Tables {
   float s2[16];    // s_v s_u, rounded once from double
   int32_t mq[16];  // quantiser multipliers (2^24 fixed point)
   int32_t dq[16];  // dequantiser factors (one fractional bit)
-  uint8_t cls[32]; // row class of each frequency
+  uint8_t cls[64]; // row class of each frequency
 };
 
 // Arguments of one pass over an image set.
@@ -84,6 +84,8 @@ enum class Mode : int { Compress = 0, Forward = 1, Inverse = 2, Decompress = 3 }
 // Kernel launchers (return hipError_t as int).
 int launch_n8(Mode mode, int kind, int dtype, const PassParams& p, hipStream_t stream);
 int launch_jam(Mode mode, int kind, int n, int dtype, const PassParams& p, hipStream_t stream);
+// The exact 8-point DCT in float32, fused zonal compress (kernels_dct.hip).
+int launch_dct8(int dtype, const PassParams& p, hipStream_t stream);
 // Quality measures (quality.hip): coefficient and pixel moments per image,
 // the measured and the AR(1) coding gain, PSNR from error energies.
 int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
@@ -94,6 +96,11 @@ int launch_coding_gain_ar1(int kind, int n, int basis, const float* rho, int cou
                            float* cg_klt, hipStream_t s);
 int launch_psnr(const unsigned long long* sse, int count, int64_t pixels, float* psnr,
                 hipStream_t s);
+// Mean SSIM of each image pair (ssim.hip); acc: batch float64 accumulators
+// (zeroed here).  APE of values against references, in percent.
+int launch_ssim(const uint8_t* x, const uint8_t* y, int batch, int height, int width,
+                int64_t pitch, int64_t image_stride, double* acc, float* out, hipStream_t s);
+int launch_ape(const float* value, const float* ref, int count, float* out, hipStream_t s);
 // Zero `words` 64-bit words with a fill kernel (no memset node in a graph).
 int launch_fill_zero(unsigned long long* p, int64_t words, hipStream_t s);
 // Fused 8x8 compress (uint8, zonal) on the int8 matrix cores; t = T[v][i] and

@@ -33,10 +33,10 @@ int ok() {
   return ADCT_OK;
 }
 
-bool valid_kind(int t) { return t >= ADCT_T1 && t <= ADCT_HT; }
+bool valid_kind(int t) { return t >= ADCT_T1 && t <= ADCT_DCT; }
 // the comparison transforms of section 4 are 8-point transforms
 bool valid_kind_n(int t, int n) { return t == ADCT_T1 || t == ADCT_T2 || n == 8; }
-bool valid_n(int n) { return n == 8 || n == 16 || n == 32; }
+bool valid_n(int n) { return n == 8 || n == 16 || n == 32 || n == 64; }
 
 // Apply the forward (inverse = false) or inverse butterfly of (kind, n) to a
 // vector on the host.
@@ -57,11 +57,13 @@ void apply_1d(int kind, int n, bool inverse, int* v) {
   } else if (kind == KIND_SIGN) {
     if (n == 8) ADCT_APPLY(KIND_SIGN, 8);
     else if (n == 16) ADCT_APPLY(KIND_SIGN, 16);
-    else ADCT_APPLY(KIND_SIGN, 32);
+    else if (n == 32) ADCT_APPLY(KIND_SIGN, 32);
+    else ADCT_APPLY(KIND_SIGN, 64);
   } else {
     if (n == 8) ADCT_APPLY(KIND_ROUND, 8);
     else if (n == 16) ADCT_APPLY(KIND_ROUND, 16);
-    else ADCT_APPLY(KIND_ROUND, 32);
+    else if (n == 32) ADCT_APPLY(KIND_ROUND, 32);
+    else ADCT_APPLY(KIND_ROUND, 64);
   }
 #undef ADCT_APPLY
 }
@@ -115,11 +117,13 @@ int build_tables(int kind, int n, int qstep, TableSet& out) {
   } else if (kind == KIND_SIGN) {
     if (n == 8) classes_of<KIND_SIGN, 8>(vals, cls);
     else if (n == 16) classes_of<KIND_SIGN, 16>(vals, cls);
-    else classes_of<KIND_SIGN, 32>(vals, cls);
+    else if (n == 32) classes_of<KIND_SIGN, 32>(vals, cls);
+    else classes_of<KIND_SIGN, 64>(vals, cls);
   } else {
     if (n == 8) classes_of<KIND_ROUND, 8>(vals, cls);
     else if (n == 16) classes_of<KIND_ROUND, 16>(vals, cls);
-    else classes_of<KIND_ROUND, 32>(vals, cls);
+    else if (n == 32) classes_of<KIND_ROUND, 32>(vals, cls);
+    else classes_of<KIND_ROUND, 64>(vals, cls);
   }
   if (vals.size() > 4) return fail(ADCT_E_ARG, "internal: more than four row classes");
   memset(&out.t, 0, sizeof(out.t));
@@ -151,6 +155,8 @@ int pixel_bytes(int dtype) { return dtype == ADCT_U8 ? 1 : 2; }
 int check_images(const char* what, int n, int dtype, const void* ptr, int batch, int height,
                  int width, int64_t pitch, int64_t image_stride, Geom& g) {
   if (dtype != ADCT_U8 && dtype != ADCT_I16) return fail(ADCT_E_ARG, "%s: bad dtype %d", what, dtype);
+  if (n == 64 && dtype != ADCT_U8)
+    return fail(ADCT_E_ARG, "%s: the 64-point transform takes 8-bit images only", what);
   if (batch < 0 || height < 0 || width < 0)
     return fail(ADCT_E_SHAPE, "%s: negative size", what);
   if (height % n || width % n)
@@ -174,7 +180,7 @@ int check_images(const char* what, int n, int dtype, const void* ptr, int batch,
 
 int check_common(int transform, int n) {
   if (!valid_kind(transform)) return fail(ADCT_E_ARG, "bad transform id %d", transform);
-  if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d (8, 16 or 32)", n);
+  if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d (8, 16, 32 or 64)", n);
   if (!valid_kind_n(transform, n))
     return fail(ADCT_E_ARG, "transform %d is an 8-point transform (n=%d)", transform, n);
   return ADCT_OK;
@@ -183,6 +189,7 @@ int check_common(int transform, int n) {
 int check_r_q(int n, int r, int qstep) {
   if (r < 1 || r > n * n) return fail(ADCT_E_ARG, "r=%d outside [1, %d]", r, n * n);
   if (qstep < 0 || qstep > 4096) return fail(ADCT_E_ARG, "qstep=%d outside [0, 4096]", qstep);
+  if (n == 64 && qstep != 0) return fail(ADCT_E_ARG, "the 64-point transform is zonal only");
   return ADCT_OK;
 }
 
@@ -194,7 +201,9 @@ int launch(Mode mode, int kind, int n, int dtype, const PassParams& p, adct_stre
       (int64_t(1) << 32))
     return fail(ADCT_E_SHAPE, "image set too large for one launch (2^32 workgroups)");
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const int e = n == 8 ? launch_n8(mode, kind, dtype, p, s) : launch_jam(mode, kind, n, dtype, p, s);
+  const int e = kind == ADCT_DCT ? launch_dct8(dtype, p, s)
+                : n == 8         ? launch_n8(mode, kind, dtype, p, s)
+                                 : launch_jam(mode, kind, n, dtype, p, s);
   if (e != hipSuccess)
     return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();
@@ -267,8 +276,12 @@ int compress_quality(const char* what, int transform, int n, int r, int qstep, c
                 (long long)words, (long long)need);
   if (static_cast<int64_t>(p.g.tiles_x) * p.g.tiles_y >= (int64_t(1) << 32))
     return fail(ADCT_E_SHAPE, "%s: more than 2^32 tiles per image", what);
+  if (transform == ADCT_DCT && (qstep != 0 || d_kept != nullptr || d_cg != nullptr))
+    return fail(ADCT_E_ARG, "%s: the DCT path is zonal, without integer coefficients or "
+                            "moments", what);
   TableSet ts;
-  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  if (transform != ADCT_DCT)
+    if (int s = build_tables(transform, n, qstep, ts)) return s;
   if (use_static_scratch)
     if (int s = static_scratch(&work)) return s;
   const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -322,6 +335,7 @@ ADCT_API const char* adct_last_error(void) { return g_last_error.c_str(); }
 
 ADCT_API int adct_get_matrix(int transform, int n, int inverse, int32_t* host_out) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "get_matrix: the DCT is not an integer matrix");
   if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
   std::vector<int> m;
   operator_matrix(transform, n, inverse != 0, m);
@@ -337,6 +351,49 @@ ADCT_API int adct_get_matrix(int transform, int n, int inverse, int32_t* host_ou
   return ok();
 }
 
+ADCT_API int adct_transform_measures(int transform, int n, double* eps, double* delta) {
+  if (int s = check_common(transform, n)) return s;
+  if (eps == nullptr && delta == nullptr) return fail(ADCT_E_ARG, "null output");
+  if (transform == ADCT_DCT) {   // the reference itself
+    if (eps) *eps = 0.0;
+    if (delta) *delta = 0.0;
+    return ok();
+  }
+  std::vector<int> t;
+  operator_matrix(transform, n, false, t);
+  std::vector<double> s(n);
+  for (int v = 0; v < n; ++v) {
+    double d = 0.0;
+    for (int i = 0; i < n; ++i) d += static_cast<double>(t[v * n + i]) * t[v * n + i];
+    s[v] = 1.0 / sqrt(d);
+  }
+  if (eps != nullptr) {
+    // pi ||C - S T||_F^2 with C the orthonormal DCT-II (section 4.1, Table 1)
+    double e = 0.0;
+    for (int v = 0; v < n; ++v)
+      for (int i = 0; i < n; ++i) {
+        const double c = sqrt(2.0 / n) * (v == 0 ? sqrt(0.5) : 1.0) *
+                         cos(v * (2 * i + 1) * M_PI / (2.0 * n));
+        const double dlt = c - s[v] * t[v * n + i];
+        e += dlt * dlt;
+      }
+    *eps = M_PI * e;
+  }
+  if (delta != nullptr) {
+    // 1 - ||diag(M)||^2 / ||M||_F^2 for M = T T^T (section 3.1)
+    double dg = 0.0, all = 0.0;
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m += static_cast<double>(t[a * n + i]) * t[b * n + i];
+        all += m * m;
+        if (a == b) dg += m * m;
+      }
+    *delta = 1.0 - dg / all;
+  }
+  return ok();
+}
+
 ADCT_API int adct_zigzag(int n, int32_t* host_out) {
   if (!valid_n(n)) return fail(ADCT_E_ARG, "bad block length %d", n);
   if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
@@ -348,6 +405,10 @@ ADCT_API int adct_zigzag(int n, int32_t* host_out) {
 ADCT_API int adct_scale_vector(int transform, int n, double* host_out) {
   if (int s = check_common(transform, n)) return s;
   if (host_out == nullptr) return fail(ADCT_E_ARG, "null output");
+  if (transform == ADCT_DCT) {   // already orthonormal
+    for (int i = 0; i < n; ++i) host_out[i] = 1.0;
+    return ok();
+  }
   std::vector<int64_t> d;
   diag_ttt(transform, n, d);
   for (int i = 0; i < n; ++i) host_out[i] = 1.0 / sqrt(static_cast<double>(d[i]));
@@ -356,6 +417,7 @@ ADCT_API int adct_scale_vector(int transform, int n, double* host_out) {
 
 ADCT_API int adct_quant_tables(int transform, int n, int qstep, int32_t* mq, int32_t* dq) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "quant_tables: the DCT path is zonal only");
   if (qstep < 1 || qstep > 4096) return fail(ADCT_E_ARG, "qstep=%d outside [1, 4096]", qstep);
   TableSet ts;
   if (int s = build_tables(transform, n, qstep, ts)) return s;
@@ -370,6 +432,7 @@ ADCT_API int adct_fwd2d(int transform, int n, const void* d_src, int dtype, int 
                         int width, int64_t pitch, int64_t image_stride, int32_t* d_coef,
                         adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "fwd2d: the DCT has no integer coefficients");
   PassParams p{};
   if (int s = check_images("fwd2d", n, dtype, d_src, batch, height, width, pitch, image_stride, p.g))
     return s;
@@ -386,6 +449,7 @@ static int inverse_common(Mode mode, int transform, int n, int r, int qstep, con
                           void* d_dst, int dtype, int batch, int height, int width, int64_t pitch,
                           int64_t image_stride, adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "inverse: the DCT has no integer coefficients");
   if (int s = check_r_q(n, r, qstep)) return s;
   PassParams p{};
   if (int s = check_images("inverse", n, dtype, d_dst, batch, height, width, pitch, image_stride, p.g))
@@ -436,8 +500,12 @@ ADCT_API int adct_compress(int transform, int n, int r, int qstep, const void* d
   if ((reinterpret_cast<uintptr_t>(d_kept) % 4) || (reinterpret_cast<uintptr_t>(d_scaled) % 4) ||
       (reinterpret_cast<uintptr_t>(d_sse) % 8))
     return fail(ADCT_E_ALIGN, "compress: misaligned output buffer");
+  if (transform == ADCT_DCT && (qstep != 0 || d_kept != nullptr))
+    return fail(ADCT_E_ARG, "compress: the DCT path is zonal and has no integer coefficients "
+                            "(qstep 0, d_kept NULL; d_scaled receives its coefficients)");
   TableSet ts;
-  if (int s = build_tables(transform, n, qstep, ts)) return s;
+  if (transform != ADCT_DCT)
+    if (int s = build_tables(transform, n, qstep, ts)) return s;
   p.t = ts.t;
   p.src = d_src;
   p.dst = d_recon;
@@ -455,6 +523,7 @@ ADCT_API int adct_compress_mfma(int transform, int r, const void* d_src, int bat
                                 adct_stream_t stream) {
   const int n = 8;
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "compress_mfma: integer transforms only");
   if (int s = check_r_q(n, r, 0)) return s;
   PassParams p{};
   if (int s = check_images("compress_mfma", n, ADCT_U8, d_src, batch, height, width, pitch,
@@ -521,6 +590,43 @@ ADCT_API int adct_compress_quality_noalloc(int transform, int n, int r, int qste
                           d_cg, basis, nullptr, kScratchWords, true, stream);
 }
 
+ADCT_API int adct_ssim(const void* d_x, const void* d_y, int batch, int height, int width,
+                       int64_t pitch, int64_t image_stride, double* d_work, float* d_ssim,
+                       adct_stream_t stream) {
+  if (batch < 0 || height < 0 || width < 0) return fail(ADCT_E_SHAPE, "ssim: negative size");
+  if (batch == 0) return ok();
+  if (height < 11 || width < 11)
+    return fail(ADCT_E_SHAPE, "ssim: %dx%d is smaller than the 11x11 window", height, width);
+  if (pitch < width) return fail(ADCT_E_SHAPE, "ssim: pitch %lld < width %d", (long long)pitch, width);
+  if (batch > 1 && image_stride < pitch * height)
+    return fail(ADCT_E_SHAPE, "ssim: image_stride %lld < pitch*height", (long long)image_stride);
+  if (d_x == nullptr || d_y == nullptr || d_work == nullptr || d_ssim == nullptr)
+    return fail(ADCT_E_ARG, "ssim: null pointer");
+  if ((reinterpret_cast<uintptr_t>(d_work) % 8) || (reinterpret_cast<uintptr_t>(d_ssim) % 4))
+    return fail(ADCT_E_ALIGN, "ssim: misaligned buffer");
+  const int e = launch_ssim(static_cast<const uint8_t*>(d_x), static_cast<const uint8_t*>(d_y),
+                            batch, height, width, pitch, image_stride, d_work, d_ssim,
+                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
+ADCT_API int adct_ape(int count, const float* d_value, const float* d_reference, float* d_ape,
+                      adct_stream_t stream) {
+  if (count < 0) return fail(ADCT_E_ARG, "ape: negative count");
+  if (count == 0) return ok();
+  if (d_value == nullptr || d_reference == nullptr || d_ape == nullptr)
+    return fail(ADCT_E_ARG, "ape: null pointer");
+  if ((reinterpret_cast<uintptr_t>(d_value) % 4) || (reinterpret_cast<uintptr_t>(d_reference) % 4) ||
+      (reinterpret_cast<uintptr_t>(d_ape) % 4))
+    return fail(ADCT_E_ALIGN, "ape: misaligned buffer");
+  const int e = launch_ape(d_value, d_reference, count, d_ape, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(ADCT_E_HIP, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  return ok();
+}
+
 ADCT_API int adct_psnr(int count, int64_t pixels, const uint64_t* d_sse, float* d_psnr,
                        adct_stream_t stream) {
   if (count < 0) return fail(ADCT_E_ARG, "psnr: negative count");
@@ -540,6 +646,7 @@ ADCT_API int adct_moments(int transform, int n, const void* d_src, int dtype, in
                           int height, int width, int64_t pitch, int64_t image_stride,
                           uint64_t* d_moments, adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "moments: integer transforms only");
   Geom g{};
   if (int s = check_images("moments", n, dtype, d_src, batch, height, width, pitch, image_stride, g))
     return s;
@@ -559,6 +666,7 @@ ADCT_API int adct_moments(int transform, int n, const void* d_src, int dtype, in
 ADCT_API int adct_coding_gain(int transform, int n, int basis, int count,
                               const uint64_t* d_moments, float* d_cg, adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "coding_gain: integer transforms only");
   if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
     return fail(ADCT_E_ARG, "coding_gain: bad basis %d", basis);
   if (count < 0) return fail(ADCT_E_ARG, "coding_gain: negative count");
@@ -578,6 +686,7 @@ ADCT_API int adct_coding_gain_ar1(int transform, int n, int basis, int count,
                                   const float* d_rho, float* d_cg, float* d_cg_klt,
                                   adct_stream_t stream) {
   if (int s = check_common(transform, n)) return s;
+  if (transform == ADCT_DCT) return fail(ADCT_E_ARG, "coding_gain_ar1: integer transforms only");
   if (basis != ADCT_BASIS_ROWS && basis != ADCT_BASIS_COLS)
     return fail(ADCT_E_ARG, "coding_gain_ar1: bad basis %d", basis);
   if (count < 0) return fail(ADCT_E_ARG, "coding_gain_ar1: negative count");

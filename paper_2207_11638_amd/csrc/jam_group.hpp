@@ -46,7 +46,7 @@ struct Cfg {
   static constexpr int TS = TPW == 32 ? odd_stride(NEED)   // LDS tile stride (words)
                                        : tile_stride(NEED, 32 / TPW);
   static constexpr int WORDS = TPW * TS;
-  static constexpr int LOG2N = N == 8 ? 3 : (N == 16 ? 4 : 5);
+  static constexpr int LOG2N = N == 8 ? 3 : (N == 16 ? 4 : (N == 32 ? 5 : 6));
   static constexpr int SROUND = 2 + 2 * LOG2N;              // divide by 4 N^2
   static_assert(TPW >= 2 && TPW <= 32, "unsupported block size");
   static_assert(KB == 4 || KB == 8 || KB == N, "unsupported kept bound");
@@ -88,12 +88,14 @@ constexpr ZigzagInv<N> make_zigzag_inv() {
 static __constant__ ZigzagInv<8> kZigzagInv8 = make_zigzag_inv<8>();
 static __constant__ ZigzagInv<16> kZigzagInv16 = make_zigzag_inv<16>();
 static __constant__ ZigzagInv<32> kZigzagInv32 = make_zigzag_inv<32>();
+static __constant__ ZigzagInv<64> kZigzagInv64 = make_zigzag_inv<64>();
 
 template <int N>
 __device__ __forceinline__ int zigzag_inv(int p) {
   if constexpr (N == 8) return kZigzagInv8.vu[p];
   else if constexpr (N == 16) return kZigzagInv16.vu[p];
-  else return kZigzagInv32.vu[p];
+  else if constexpr (N == 32) return kZigzagInv32.vu[p];
+  else return kZigzagInv64.vu[p];
 }
 
 // Fill the tables of one workgroup.  Thread p < r writes zig-zag entry p from

@@ -225,9 +225,44 @@ hipError_t launch_n(Mode mode, int dtype, const PassParams& p, hipStream_t s) {
                         : launch_typed<KIND, N, DT_I16>(mode, p, s);
 }
 
+// 64-point level of the recursion: 8-bit input and zonal retention only (the
+// int32 intermediates of its inverse are exact for 8-bit input, not over the
+// whole int16 range); the host refuses the other cases.
+template <int KIND>
+hipError_t launch_64(Mode mode, const PassParams& p_in, hipStream_t s) {
+  constexpr int N = 64;
+  using C = Cfg<N>;
+  PassParams p = p_in;
+  const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
+  p.gpw = mode == Mode::Compress
+              ? groups_per_wg(groups_x, static_cast<int64_t>(p.g.tiles_y) * p.g.batch)
+              : 1;
+  const dim3 grid((groups_x + p.gpw - 1) / p.gpw, p.g.tiles_y, p.g.batch);
+  switch (mode) {
+    case Mode::Compress:
+      if (p.r <= 10) compress_jam<KIND, N, DT_U8, false, 4><<<grid, kBlock, 0, s>>>(p);
+      else if (p.r <= 36) compress_jam<KIND, N, DT_U8, false, 8><<<grid, kBlock, 0, s>>>(p);
+      else compress_jam<KIND, N, DT_U8, false, N><<<grid, kBlock, 0, s>>>(p);
+      break;
+    case Mode::Forward:
+      forward_jam<KIND, N, DT_U8><<<grid, kBlock, 0, s>>>(p);
+      break;
+    case Mode::Inverse:
+      inverse_jam<KIND, N, DT_U8, false, false><<<grid, kBlock, 0, s>>>(p);
+      break;
+    case Mode::Decompress:
+      inverse_jam<KIND, N, DT_U8, false, true><<<grid, kBlock, 0, s>>>(p);
+      break;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int launch_jam(Mode mode, int kind, int n, int dtype, const PassParams& p, hipStream_t stream) {
+  if (n == 64)
+    return kind == KIND_SIGN ? launch_64<KIND_SIGN>(mode, p, stream)
+                             : launch_64<KIND_ROUND>(mode, p, stream);
   if (kind == KIND_SIGN)
     return n == 16 ? launch_n<KIND_SIGN, 16>(mode, dtype, p, stream)
                    : launch_n<KIND_SIGN, 32>(mode, dtype, p, stream);

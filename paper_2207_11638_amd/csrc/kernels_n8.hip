@@ -134,12 +134,18 @@ dim3 grid_for(const Geom& g) {
   return dim3((g.tiles_x + kWave - 1) / kWave, g.tiles_y, g.batch);
 }
 
+// The comparison transforms take a coarser set of bounds (fewer kernels to
+// build); any bound >= r gives the same result.
+constexpr bool coarse_rb(int rb) { return rb == 10 || rb == 28 || rb == 64; }
+
 template <int KIND, int DT, int I>
 void launch_compress_rb(const PassParams& p, hipStream_t s, dim3 grid) {
   if constexpr (I < kNumRB) {
-    if (p.r <= kRB[I]) {
-      compress8<KIND, DT, kRB[I], false><<<grid, kWave, 0, s>>>(p);
-      return;
+    if constexpr (KIND <= KIND_ROUND || coarse_rb(kRB[I])) {
+      if (p.r <= kRB[I]) {
+        compress8<KIND, DT, kRB[I], false><<<grid, kWave, 0, s>>>(p);
+        return;
+      }
     }
     launch_compress_rb<KIND, DT, I + 1>(p, s, grid);
   }

@@ -82,6 +82,8 @@ static __constant__ TransformInfo<32> kInfo1_32 = make_info<KIND_SIGN, 32>();
 static __constant__ TransformInfo<8> kInfo2_8 = make_info<KIND_ROUND, 8>();
 static __constant__ TransformInfo<16> kInfo2_16 = make_info<KIND_ROUND, 16>();
 static __constant__ TransformInfo<32> kInfo2_32 = make_info<KIND_ROUND, 32>();
+static __constant__ TransformInfo<64> kInfo1_64 = make_info<KIND_SIGN, 64>();
+static __constant__ TransformInfo<64> kInfo2_64 = make_info<KIND_ROUND, 64>();
 static __constant__ TransformInfo<8> kInfoWHT = make_info<KIND_WHT, 8>();
 static __constant__ TransformInfo<8> kInfoSDCT = make_info<KIND_SDCT, 8>();
 static __constant__ TransformInfo<8> kInfoHT = make_info<KIND_HT, 8>();
@@ -97,11 +99,13 @@ __device__ __forceinline__ const TransformInfo<N>& info() {
   } else if constexpr (KIND == KIND_SIGN) {
     if constexpr (N == 8) return kInfo1_8;
     else if constexpr (N == 16) return kInfo1_16;
-    else return kInfo1_32;
+    else if constexpr (N == 32) return kInfo1_32;
+    else return kInfo1_64;
   } else {
     if constexpr (N == 8) return kInfo2_8;
     else if constexpr (N == 16) return kInfo2_16;
-    else return kInfo2_32;
+    else if constexpr (N == 32) return kInfo2_32;
+    else return kInfo2_64;
   }
 }
 
@@ -409,7 +413,8 @@ hipError_t launch_cg_typed(int n, const unsigned long long* mom, int count, int 
                            hipStream_t s) {
   if (n == 8) coding_gain_kernel<KIND, 8><<<count, kBlock, 0, s>>>(mom, basis, cg);
   else if (n == 16) coding_gain_kernel<KIND, 16><<<count, kBlock, 0, s>>>(mom, basis, cg);
-  else coding_gain_kernel<KIND, 32><<<count, kBlock, 0, s>>>(mom, basis, cg);
+  else if (n == 32) coding_gain_kernel<KIND, 32><<<count, kBlock, 0, s>>>(mom, basis, cg);
+  else coding_gain_kernel<KIND, 64><<<count, kBlock, 0, s>>>(mom, basis, cg);
   return hipGetLastError();
 }
 
@@ -418,7 +423,8 @@ hipError_t launch_ar1_typed(int n, const float* rho, int count, int basis, float
                             float* cg_klt, hipStream_t s) {
   if (n == 8) coding_gain_ar1_kernel<KIND, 8><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
   else if (n == 16) coding_gain_ar1_kernel<KIND, 16><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
-  else coding_gain_ar1_kernel<KIND, 32><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+  else if (n == 32) coding_gain_ar1_kernel<KIND, 32><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
+  else coding_gain_ar1_kernel<KIND, 64><<<count, 64, 0, s>>>(rho, count, basis, cg, cg_klt);
   return hipGetLastError();
 }
 
@@ -441,6 +447,12 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
   if (kind == KIND_WHT) return launch_moments_typed<KIND_WHT, 8>(dtype, p, s);
   if (kind == KIND_SDCT) return launch_moments_typed<KIND_SDCT, 8>(dtype, p, s);
   if (kind == KIND_HT) return launch_moments_typed<KIND_HT, 8>(dtype, p, s);
+  if (n == 64) {   // 8-bit input only (the host refuses the rest)
+    const dim3 grid(p.wpi, p.g.batch);
+    if (kind == KIND_SIGN) moments_kernel<KIND_SIGN, 64, DT_U8><<<grid, kBlock, 0, s>>>(p);
+    else moments_kernel<KIND_ROUND, 64, DT_U8><<<grid, kBlock, 0, s>>>(p);
+    return hipGetLastError();
+  }
   if (kind == KIND_SIGN) {
     if (n == 8) return launch_moments_typed<KIND_SIGN, 8>(dtype, p, s);
     if (n == 16) return launch_moments_typed<KIND_SIGN, 16>(dtype, p, s);

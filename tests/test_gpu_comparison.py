@@ -123,3 +123,78 @@ def test_ordering_of_reconstruction_quality():
         assert abs(psnr[kind] - want) <= 1e-5 * abs(want)
     assert psnr[M.ROUND] > psnr[M.SIGN] and psnr[M.ROUND] > psnr[M.SDCT]
     assert psnr[M.WHT] > psnr[M.HT] and psnr[M.SDCT] > psnr[M.HT]
+
+
+# ------------------------------------------------- the exact DCT in float32
+def check_dct(imgs, r, out):
+    """Float32 DCT against the float64 oracle.  Coefficients: per tile,
+    max |c - c64| <= 1e-5 * ||A||_2 (the tile's energy, equal to that of its
+    coefficients); reconstruction: exact except where the float64 value lies
+    within 1e-2 of a rounding tie, where either neighbour is accepted; error
+    energy: exactly the one of the kernel's own reconstruction, and within the
+    ambiguous pixels' slack of the oracle's; PSNR within 1e-5 relative."""
+    sc = host(out["scaled"]).astype(np.float64)
+    rec = host(out["recon"])
+    sse = host(out["sse"]).astype(np.int64)
+    for i, im in enumerate(imgs):
+        want = P.compress_dct(im, r)
+        a = P.to_tiles(P.level_shift(im), 8).astype(np.float64)
+        norm = np.sqrt((a ** 2).sum(axis=(2, 3)))[..., None]
+        err = np.abs(sc[i] - want["scaled"])
+        assert np.all(err <= 1e-5 * np.maximum(norm, 1.0)), err.max()
+        amb = want["margin"] < 1e-2
+        diff = rec[i].astype(np.int64) - want["recon"].astype(np.int64)
+        assert np.all(diff[~amb] == 0)
+        assert np.all(np.abs(diff[amb]) <= 1)
+        own = int(((rec[i].astype(np.int64) - im.astype(np.int64)) ** 2).sum())
+        assert sse[i] == own
+        slack = int((2 * np.abs(im.astype(np.int64) - want["recon"].astype(np.int64))[amb] + 1).sum())
+        assert abs(own - want["sse"]) <= slack
+        if want["sse"]:
+            got_p = 10 * np.log10(255.0 ** 2 * im.size / own) if own else np.inf
+            assert abs(got_p - want["psnr"]) <= 1e-5 * abs(want["psnr"]) or amb.any()
+
+
+@pytest.mark.parametrize("r", [1, 6, 10, 15, 28, 45, 64])
+def test_dct_float32_u8(r):
+    imgs = u8_images(2, 3600)
+    out = adct.compress(to_dev(np.stack(imgs)), adct.ADCT_DCT, 8, r)
+    assert out["kept"] is None
+    check_dct(imgs, r, out)
+
+
+@pytest.mark.parametrize("r", [1, 10, 64])
+def test_dct_float32_i16(r):
+    imgs = i16_images(1, 3700)
+    out = adct.compress(to_dev(np.stack(imgs)), adct.ADCT_DCT, 8, r)
+    check_dct(imgs, r, out)
+
+
+def test_dct_psnr_and_ape():
+    """The reference PSNR of section 5 and the absolute percentage error of
+    the approximations relative to it (section 5.1), on one 512 x 512 image."""
+    img = synth.ar1_image(512, 512, rho=0.95, seed=0)
+    x = to_dev(img)
+    ref = adct.compress_quality(x, adct.ADCT_DCT, 8, 10)
+    assert ref["kept"] is None and ref["coding_gain"] is None
+    want = P.compress_dct(img, 10)["psnr"]
+    got = float(host(ref["psnr"])[0])
+    assert abs(got - want) <= 1e-5 * want
+    for kind in M.KINDS:
+        p = float(host(adct.compress_quality(x, kind, 8, 10)["psnr"])[0])
+        ape = 100.0 * abs(p - got) / got
+        want_ape = 100.0 * abs(P.compress(img, kind, 8, 10)["psnr"] - want) / want
+        assert abs(ape - want_ape) <= 1e-3
+
+
+def test_dct_rejects_integer_only_requests():
+    x = to_dev(np.zeros((8, 8), np.uint8))
+    kept = torch.empty((1, 1, 1, 10), dtype=torch.int32, device=DEV)
+    with pytest.raises(adct.AdctError):
+        adct.compress(x, adct.ADCT_DCT, 8, 10, kept=kept)
+    with pytest.raises(adct.AdctError):
+        adct.compress(x, adct.ADCT_DCT, 8, 10, 16)
+    with pytest.raises(adct.AdctError):
+        adct.fwd2d(x, adct.ADCT_DCT, 8)
+    with pytest.raises(adct.AdctError):
+        adct.compress(to_dev(np.zeros((16, 16), np.uint8)), adct.ADCT_DCT, 16, 10)

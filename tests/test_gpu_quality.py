@@ -220,3 +220,59 @@ def test_compress_quality_workspace_checks():
     torch.cuda.synchronize()
     want = P.compress(host(x), 1, 8, 10)
     assert close(host(psnr)[0], want["psnr"])
+
+
+# ------------------------------------------------------------- SSIM and APE
+@pytest.mark.parametrize("h,w", [(64, 80), (75, 201), (11, 11), (130, 70)])
+def test_ssim_matches_oracle(h, w):
+    """Mean SSIM of an image and its reconstructions (r = 1, 10 and exact)
+    against the float64 oracle; windows span several workgroups with ragged
+    edges in both directions."""
+    img = synth.ar1_image(h, w, rho=0.93, seed=h + w)
+    x = to_dev(np.stack([img, img, img]))
+    recs = []
+    for r in (1, 10, 64):
+        recs.append(P.compress(img, 2, 8, r)["recon"] if h % 8 == 0 and w % 8 == 0 else
+                    np.clip(img.astype(np.int16) + np.random.default_rng(r).integers(
+                        -r // 4 - 1, r // 4 + 2, size=img.shape), 0, 255).astype(np.uint8))
+    y = to_dev(np.stack(recs))
+    got = host(adct.ssim(x, y))
+    for i, rec in enumerate(recs):
+        want = MT.mean_ssim(img, rec)
+        assert close(got[i], want), (got[i], want)
+
+
+def test_ssim_identical_and_constant_images():
+    img = synth.ar1_image(40, 48, rho=0.9, seed=9)
+    x = to_dev(img)
+    assert abs(float(host(adct.ssim(x, x))[0]) - 1.0) <= 1e-6
+    a = to_dev(np.full((24, 24), 200, np.uint8))
+    b = to_dev(np.full((24, 24), 10, np.uint8))
+    c1 = (0.01 * 255) ** 2
+    want = (2 * 200 * 10 + c1) / (200 ** 2 + 10 ** 2 + c1)
+    assert close(host(adct.ssim(a, b))[0], want)
+
+
+def test_ssim_and_ape_of_the_still_image_experiment():
+    """Section 5.1 on one 512 x 512 AR(1) image: PSNR and SSIM of T1 and T2
+    reconstructions at r = 6, and their APE relative to the exact DCT."""
+    img = synth.ar1_image(512, 512, rho=0.95, seed=0)
+    x = to_dev(img)
+    ref = adct.compress(x, adct.ADCT_DCT, 8, 6, scaled=False)
+    ref_ssim = adct.ssim(x, ref["recon"])
+    want_ref = MT.mean_ssim(img, P.compress_dct(img, 6)["recon"])
+    assert abs(float(host(ref_ssim)[0]) - want_ref) <= 1e-4   # float32 DCT: ties may round apart
+    for kind in M.KINDS:
+        out = adct.compress(x, kind, 8, 6, scaled=False)
+        s = adct.ssim(x, out["recon"])
+        want = MT.mean_ssim(img, P.compress(img, kind, 8, 6)["recon"])
+        assert close(host(s)[0], want)
+        ape = host(adct.ape(s, ref_ssim))[0]
+        want_ape = MT.absolute_percentage_error(want, float(host(ref_ssim)[0]))
+        assert abs(ape - want_ape) <= 1e-4 * max(want_ape, 1.0)
+
+
+def test_ssim_rejects_small_images():
+    x = to_dev(np.zeros((10, 40), np.uint8))
+    with pytest.raises(adct.AdctError):
+        adct.ssim(x, x)

@@ -246,3 +246,18 @@ def test_quantised_8point_path_fits_int32_for_full_range_int16(kind):
         assert max(col, row) <= INT32, (q, col, row)
         bmax = np.abs(T).sum(1).max() ** 2 * XMAX
         assert bmax * mq.max() / 2 ** 24 + 1 < 2 ** 23 and dq.max() < 2 ** 23
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+def test_64_point_level_fits_int32_for_8bit_input_only(kind):
+    # the forward passes see unshifted pixels (<= 255, the shift is folded
+    # into the DC coefficient), the inverse the coefficients of x - 128
+    n = 64
+    T = M.transform_matrix(kind, n)
+    row = peak(fwd, unit(n), kind)
+    assert row * np.abs(T).sum(1).max() * 255 <= INT32
+    rs = (1, 10, 36, 100, 500, 1000, 2000, 3000, 4096)
+    worst = max(max(inverse_peaks(kind, n, mask(n, r))) for r in rs)
+    assert worst * 128 <= INT32
+    # and the whole int16 range would not fit: the library refuses it at N = 64
+    assert worst * XMAX > INT32

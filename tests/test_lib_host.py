@@ -79,8 +79,9 @@ def _compress(lib, **kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(transform=6), -1), (dict(transform=0), -1), (dict(transform=3, n=16), -1),
-    (dict(transform=4, n=32), -1), (dict(n=4), -1), (dict(n=64), -1),
+    (dict(transform=7), -1), (dict(transform=0), -1), (dict(transform=3, n=16), -1),
+    (dict(transform=4, n=32), -1), (dict(n=4), -1), (dict(n=128), -1),
+    (dict(n=64, dtype=1, pitch=64), -1), (dict(n=64, qstep=8), -1), (dict(n=64, transform=3), -1),
     (dict(r=0), -1), (dict(r=65), -1), (dict(n=16, r=257), -1), (dict(qstep=-1), -1),
     (dict(qstep=4097), -1), (dict(dtype=2), -1), (dict(src=None), -1),
     (dict(height=60), -2), (dict(width=20, pitch=20), -2), (dict(pitch=32), -2),
@@ -104,7 +105,7 @@ def test_empty_image_sets_are_a_no_op(lib):
 def test_mfma_entry_point_validates(lib):
     p = C.c_void_p(4096)
     #                              T  r   src  B  H   W   pitch stride kept scaled recon sse
-    assert lib.adct_compress_mfma(6, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
+    assert lib.adct_compress_mfma(7, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 0, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 65, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
     assert lib.adct_compress_mfma(1, 10, None, 1, 64, 64, 64, 4096, None, None, None, None,
@@ -138,7 +139,7 @@ def test_quality_entry_points_validate(lib):
     assert lib.adct_psnr(3, 64, C.c_void_p(4100), p, None) == -3
     assert lib.adct_psnr(0, 64, None, None, None) == 0
     # moments: transform, n, shape, record alignment, more than 2^32 tiles is refused
-    assert lib.adct_moments(6, 8, p, 0, 1, 8, 8, 8, 64, p, None) == -1
+    assert lib.adct_moments(7, 8, p, 0, 1, 8, 8, 8, 64, p, None) == -1
     assert lib.adct_moments(3, 16, p, 0, 1, 16, 16, 16, 256, p, None) == -1
     assert lib.adct_moments(1, 12, p, 0, 1, 12, 12, 12, 144, p, None) == -1
     assert lib.adct_moments(1, 8, p, 0, 1, 12, 8, 8, 96, p, None) == -2
@@ -155,6 +156,23 @@ def test_quality_entry_points_validate(lib):
     assert lib.adct_coding_gain_ar1(2, 16, 0, 1, None, p, p, None) == -1
     assert lib.adct_coding_gain_ar1(2, 16, 0, 4, p, None, None, None) == 0
     assert lib.adct_coding_gain_ar1(2, 16, 0, 4, C.c_void_p(4098), p, None, None) == -3
+
+
+def test_dct_entry_points_validate(lib):
+    # the exact DCT (float32) is 8-point, zonal, without integer coefficients
+    p = C.c_void_p(4096)
+    out = np.zeros(64, dtype=np.int32)
+    assert lib.adct_get_matrix(6, 8, 0, out.ctypes.data) == -1
+    assert lib.adct_quant_tables(6, 8, 16, out.ctypes.data, out.ctypes.data) == -1
+    assert np.array_equal(adct.scale_vector(6, 8), np.ones(8))
+    assert _compress(lib, transform=6, kept=p) == -1
+    assert _compress(lib, transform=6, qstep=8) == -1
+    assert _compress(lib, transform=6, n=16, pitch=64) == -1
+    assert lib.adct_fwd2d(6, 8, p, 0, 1, 8, 8, 8, 64, p, None) == -1
+    assert lib.adct_inv2d(6, 8, 10, 0, p, p, 0, 1, 8, 8, 8, 64, None) == -1
+    assert lib.adct_moments(6, 8, p, 0, 1, 8, 8, 8, 64, p, None) == -1
+    assert lib.adct_coding_gain_ar1(6, 8, 1, 1, p, p, None, None) == -1
+    assert lib.adct_compress_mfma(6, 10, p, 1, 64, 64, 64, 4096, None, None, None, None, None) == -1
 
 
 def test_python_front_end_refuses_host_tensors():
@@ -232,3 +250,27 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing" / "libadct.so"))
     with pytest.raises(RuntimeError, match="missing"):
         L.load()
+
+
+@pytest.mark.parametrize("kind,n", [(k, n) for k in M.KINDS for n in M.SIZES] +
+                         [(k, 8) for k in M.COMPARISON_KINDS])
+def test_transform_measures_match_the_oracle(kind, n):
+    from oracle import metrics as Q
+    eps, delta = adct.transform_measures(kind, n)
+    want_eps = Q.total_error_energy(M.dct2_matrix(n), M.near_orthogonal(kind, n))
+    t = M.transform_matrix(kind, n)
+    want_delta = Q.deviation_from_diagonality(t @ t.T)
+    assert eps == pytest.approx(want_eps, rel=1e-12, abs=1e-12)
+    assert delta == pytest.approx(want_delta, rel=1e-12, abs=1e-15)
+
+
+def test_transform_measures_reproduce_table1(paper_values):
+    v = paper_values["total_error_energy"]
+    assert round(adct.transform_measures(M.ROUND, 8)[0], 2) == v["round_8"]
+    assert round(adct.transform_measures(M.SIGN, 8)[0], 2) == v["sign_8"]
+    assert round(adct.transform_measures(M.SDCT, 8)[0], 2) == v["sdct_8"]
+    assert round(adct.transform_measures(M.WHT, 8)[0], 2) == 5.05
+    assert round(adct.transform_measures(M.HT, 8)[0], 2) == 47.61
+    assert adct.transform_measures(M.SIGN, 8)[1] == pytest.approx(1 / 14, abs=1e-15)
+    assert adct.transform_measures(M.ROUND, 8)[1] == pytest.approx(4 / 69, abs=1e-15)
+    assert adct.transform_measures(6, 8) == (0.0, 0.0)
