@@ -36,7 +36,8 @@ N = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_compress8_c1.json")
 KERNEL_SOURCES = ("paper_2207_11638_amd/csrc/kernels_n8.hip",
                   "paper_2207_11638_amd/csrc/tile8.hpp",
-                  "paper_2207_11638_amd/csrc/butterflies.hpp")
+                  "paper_2207_11638_amd/csrc/butterflies.hpp",
+                  "paper_2207_11638_amd/csrc/adct_internal.hpp")
 
 
 def algorithmic_bytes(b, h, w, r):
@@ -637,7 +638,7 @@ def run_ceiling(args):
     results = {}
     for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
         best = None
-        for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+        for blocks in (2048, 8192, 16384, 32768, 65536):
             for unroll in ((1,) if pattern == 1 else (1, 2, 4, 8)):
                 def go():
                     _lib.check(lib.adct_stream_ceiling(pattern, C.c_void_p(dst.data_ptr()),

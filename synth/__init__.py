@@ -86,7 +86,7 @@ def _to_u8(y: np.ndarray, sigma: float, mean: float) -> np.ndarray:
     t += 0.5
     np.floor(t, out=t)
     np.clip(t, 0, 255, out=t)
-    return t.astype(np.uint8)
+    return t.astype(np.uint8, order="C")   # row-major whatever the filter's layout
 
 
 def ar1_field(h: int, w: int, rho: float, rng: np.random.Generator) -> np.ndarray:
