@@ -407,18 +407,31 @@ ADCT_API int adct_batch_run(adct_batch_t* plan, const void* d_src, void* d_dst, 
  * (synchronising the stream), keeps the fastest and writes it to
  * chosen[bucket] (chosen may be NULL); it then times the tuned per-bucket
  * sequence against the unified launch and keeps the faster as the sequence
- * ADCT_RUN_GRAPH captures (the unified launch until a plan is tuned).  When
+ * ADCT_RUN_GRAPH captures (the unified launch until a plan is tuned).  For
+ * the row-per-thread unified launch it also times the tile groups per item of
+ * 8x8 and 16x16 TUs (1, 2 or 4) and a persistent grid (4 or 8 resident
+ * workgroups per compute unit walking XCD slices of the items) against one
+ * workgroup per item, and keeps the fastest.  When
  * the environment variable ADCT_TUNE_CACHE names a file, choices are cached
  * there keyed by device architecture and plan shape and reused by later
  * plans. */
 ADCT_API int adct_batch_set_shape(adct_batch_t* plan, int bs8, int bs_jam);
+/* The row-per-thread unified launch's shape (what adct_batch_tune searches):
+ * tile groups per work item for 8x8 and for 16x16 TUs (1, 2, 4 or 8; a 32x32
+ * item holds one group), and persistent = 1 for a grid of wgs_per_cu (1..16)
+ * workgroups per compute unit that walk the items instead of one workgroup
+ * per item.  Rebuilds the plan's unified work list (synchronises). */
+ADCT_API int adct_batch_set_small_shape(adct_batch_t* plan, int groups8, int groups16,
+                                        int persistent, int wgs_per_cu);
 ADCT_API int adct_batch_tune(adct_batch_t* plan, const void* d_src, void* d_dst, int32_t* d_kept,
                              float* d_scaled, uint64_t* d_sse, adct_stream_t stream, int* chosen);
 
-/* Work-list statistics (bookkeeping): out[0..9] = images, TUs, work items,
+/* Work-list statistics (bookkeeping): out[0..13] = images, TUs, work items,
  * items of size 8, 16 and 32, buckets, compute units of the device, items
- * of the unified launches, and 1 when the zonal unified launch is the
- * row-per-thread form for kept bounds <= 8 (else 0). */
+ * of the unified launches, 1 when the zonal unified launch is the
+ * row-per-thread form for kept bounds <= 8 (else 0), that form's tile groups
+ * per item for 8x8 and for 16x16 TUs, 1 when it runs as a persistent grid,
+ * and the persistent grid's workgroups per compute unit. */
 ADCT_API int adct_batch_info(const adct_batch_t* plan, int64_t* out);
 
 /* ----------------------------------------------------------------------

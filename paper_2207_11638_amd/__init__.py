@@ -384,14 +384,21 @@ class BatchPlan:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(10, dtype=np.int64)
+        out = np.zeros(14, dtype=np.int64)
         _lib.check(_lib.load().adct_batch_info(self._h, out.ctypes.data))
         keys = ("images", "tus", "items", "items8", "items16", "items32", "buckets", "cus",
-                "unified_items", "small_bound")
+                "unified_items", "small_bound", "small_groups8", "small_groups16",
+                "persistent", "wgs_per_cu")
         return dict(zip(keys, out.tolist()))
 
     def set_shape(self, bs8: int, bs_jam: int):
         _lib.check(_lib.load().adct_batch_set_shape(self._h, bs8, bs_jam))
+
+    def set_small_shape(self, groups8: int, groups16: int, persistent: bool = False,
+                        wgs_per_cu: int = 8):
+        """Shape of the row-per-thread unified launch (see adct.h)."""
+        _lib.check(_lib.load().adct_batch_set_small_shape(self._h, groups8, groups16,
+                                                          int(persistent), wgs_per_cu))
 
     def tune(self, src, dst=None, kept=None, scaled=None, sse=None):
         _require_device(src, dst, kept, scaled, sse)

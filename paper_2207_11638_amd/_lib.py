@@ -49,6 +49,7 @@ _SIGNATURES = {
     "adct_batch_destroy": ([_vp], _i32),
     "adct_batch_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
     "adct_batch_set_shape": ([_vp, _i32, _i32], _i32),
+    "adct_batch_set_small_shape": ([_vp, _i32, _i32, _i32, _i32], _i32),
     "adct_batch_tune": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "adct_batch_info": ([_vp, _vp], _i32),
     "adct_server_create": ([_i64, _i32, _i32, _vp, _vp], _i32),

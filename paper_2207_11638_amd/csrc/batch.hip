@@ -20,8 +20,10 @@
 // replayed, or, as a baseline, issued as one launch per image and bucket.
 //
 // Shape.  The workgroup size of every bucket (8x8: 64 or 256 threads; 16x16
-// and 32x32: 128 or 256) is chosen by adct_batch_tune, which times the
-// candidates on the caller's buffers and caches the choice.
+// and 32x32: 128 or 256), and for the small-bound unified launch the tile
+// groups per item of 8x8 and 16x16 TUs and the one-shot or persistent grid,
+// are chosen by adct_batch_tune, which times the candidates on the caller's
+// buffers and caches the choice.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -207,6 +209,7 @@ struct UnifiedParams {
   unsigned long long* sse;
   const BItem* items;
   const UBucket* buckets;
+  int n_items;          // items of the launch (the persistent form walks them)
 };
 
 constexpr int kUnifiedWords = 256 * 33 > jam::Cfg<32, 256>::WORDS ? 256 * 33
@@ -280,7 +283,10 @@ __global__ __launch_bounds__(256) void bucket_unified(UnifiedParams p) {
 // loaded once and one error-energy atomic per item.  The 32x32 item stays a
 // single group: the group loop would keep enough state live to cost 30
 // registers, and the launch's occupancy is set by its largest path.
-constexpr int kSmallGroups[3] = {2, 2, 1};   // groups per item, n = 8, 16, 32
+// Groups per item compiled for n = 8, 16, 32: more than one (a loop over the
+// item's groups, any count) for 8 and 16, exactly one for 32.  The plan's
+// item size (adct_batch::small_groups, tuned) sets the count at run time.
+constexpr int kSmallGroups[3] = {2, 2, 1};
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kSmallWords =
@@ -333,11 +339,9 @@ __device__ __forceinline__ void item_rows(const Outs& o, const BItem& it, const 
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void bucket_unified_small(UnifiedParams p) {
-  __shared__ int S[kSmallWords];
-  __shared__ SmallShared sh;
-  __shared__ unsigned long long red[4];
-  const BItem it = p.items[xcd_slice_item(blockIdx.x, gridDim.x)];
+__device__ __forceinline__ void small_item(const UnifiedParams& p, int idx, int* S,
+                                           SmallShared& sh, unsigned long long* red) {
+  const BItem it = p.items[idx];
   const UBucket& b = p.buckets[it.pad];
   const Outs o{p.imgs, p.pos, p.src, p.dst, p.kept, p.scaled, p.sse};
   constexpr int G8 = kSmallGroups[0], G16 = kSmallGroups[1], G32 = kSmallGroups[2];
@@ -352,6 +356,31 @@ __global__ __launch_bounds__(256) void bucket_unified_small(UnifiedParams p) {
     case 7: item_rows<DT, KIND_ROUND, 32, 256, 4, G32>(o, it, b.t, S, sh.n32, red); break;
     case 8: item_rows<DT, KIND_SIGN, 32, 256, 8, G32>(o, it, b.t, S, sh.n32, red); break;
     default: item_rows<DT, KIND_ROUND, 32, 256, 8, G32>(o, it, b.t, S, sh.n32, red); break;
+  }
+}
+
+// One-shot (one workgroup per item, XCD-sliced order) or persistent: a grid
+// of 8 J resident workgroups in which the J workgroups of XCD x walk that
+// XCD's contiguous slice of the ordered items with stride J, so the slices
+// stay on their L2 and no workgroup is dispatched per item.  The persistent
+// grid is a multiple of 8 (the host rounds it).
+template <int DT, bool PERSIST>
+__global__ __launch_bounds__(256) void bucket_unified_small(UnifiedParams p) {
+  __shared__ int S[kSmallWords];
+  __shared__ SmallShared sh;
+  __shared__ unsigned long long red[4];
+  if constexpr (!PERSIST) {
+    small_item<DT>(p, xcd_slice_item(blockIdx.x, gridDim.x), S, sh, red);
+  } else {
+    const int g = p.n_items;
+    const int q = g / kXcds, m = g - q * kXcds;
+    const int x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const int stride = gridDim.x / kXcds;
+    const int begin = x * q + min(x, m), end = begin + q + (x < m ? 1 : 0);
+    for (int i = begin + j; i < end; i += stride) {
+      small_item<DT>(p, i, S, sh, red);
+      __syncthreads();   // the next item reuses the tables and the exchange area
+    }
   }
 }
 
@@ -463,6 +492,13 @@ struct adct_batch {
   std::vector<Unified> unified;
   UBucket* d_ubuckets = nullptr;
   bool prefer_unified = true;       // the sequence a graph replays (chosen by tune)
+  // small-bound unified launch: tile groups per item for 8x8 and 16x16 TUs
+  // (32x32 items hold one group), and the persistent form with its resident
+  // workgroups per CU; all chosen by adct_batch_tune
+  int small_groups[2] = {2, 2};
+  bool persistent = false;
+  int wgs_per_cu = 8;
+  std::vector<int2> pos;            // TU positions in the sorted order (item rebuilds)
   // graph cache
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -563,7 +599,8 @@ hipError_t build_unified(adct_batch* b, const std::vector<int2>& pos) {
       b->unified.back().quant = quant;
       b->unified.back().small = !quant && small;
     }
-    const int cap = b->unified[u].small ? (256 >> k.log2n) * kSmallGroups[k.log2n - 3]
+    const int groups = k.log2n == 5 ? 1 : b->small_groups[k.log2n - 3];
+    const int cap = b->unified[u].small ? (256 >> k.log2n) * groups
                                         : (k.log2n == 3 ? 256 : 256 >> k.log2n);
     int64_t t = k.tu_begin;
     while (t < k.tu_end) {
@@ -608,8 +645,20 @@ void launch_unified(const adct_batch* b, const adct_batch::Unified& u, const Uni
   if (u.items.empty()) return;
   const dim3 grid(static_cast<unsigned>(u.items.size()));
   if (u.small) {
-    if (b->dtype == ADCT_U8) bucket_unified_small<DT_U8><<<grid, 256, 0, s>>>(p);
-    else bucket_unified_small<DT_I16><<<grid, 256, 0, s>>>(p);
+    UnifiedParams q = p;
+    q.n_items = static_cast<int>(u.items.size());
+    if (b->persistent) {
+      // resident workgroups, a multiple of the 8 XCDs, at most one per item
+      int64_t wg = static_cast<int64_t>(b->cus) * b->wgs_per_cu;
+      wg = std::min<int64_t>(wg, (q.n_items + kXcds - 1) / kXcds * kXcds);
+      wg = std::max<int64_t>(kXcds, wg / kXcds * kXcds);
+      const dim3 pg(static_cast<unsigned>(wg));
+      if (b->dtype == ADCT_U8) bucket_unified_small<DT_U8, true><<<pg, 256, 0, s>>>(q);
+      else bucket_unified_small<DT_I16, true><<<pg, 256, 0, s>>>(q);
+      return;
+    }
+    if (b->dtype == ADCT_U8) bucket_unified_small<DT_U8, false><<<grid, 256, 0, s>>>(q);
+    else bucket_unified_small<DT_I16, false><<<grid, 256, 0, s>>>(q);
     return;
   }
   if (b->dtype == ADCT_U8) {
@@ -644,7 +693,7 @@ hipError_t enqueue_run(const adct_batch* b, const void* src, void* dst, int32_t*
   if (sse != nullptr && nb > 0) zero_u64<<<nb, 256, 0, s>>>(sse_dev, b->n_images);
   if (mode == ADCT_RUN_UNIFIED) {
     UnifiedParams up{b->d_imgs, b->d_pos, src, dst, kept, scaled, sse_dev, nullptr,
-                     b->d_ubuckets};
+                     b->d_ubuckets, 0};
     for (const auto& u : b->unified) {
       up.items = u.d_items;
       launch_unified(b, u, up, s);
@@ -667,13 +716,24 @@ hipError_t enqueue_run(const adct_batch* b, const void* src, void* dst, int32_t*
   return hipGetLastError();
 }
 
+// Images with TUs in [tu_begin, tu_end) (TUs of a bucket are sorted by image).
+int bucket_images(const adct_batch* b, const Bucket& k) {
+  int n = 0;
+  for (int64_t t = k.tu_begin; t < k.tu_end; ++t)
+    if (t == k.tu_begin || b->tu_image[t] != b->tu_image[t - 1]) ++n;
+  return n;
+}
+
 std::string tune_key(const adct_batch* b, const Bucket& k) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s:dt%d:n%d:k%d:q%d:st%d:tus%lld:img%d", b->arch.c_str(), b->dtype,
-           8 << (k.log2n - 3), k.kind, k.qstep, int(k.staged) + 2 * k.kb,
-           (long long)(k.tu_end - k.tu_begin), static_cast<int>(k.image_ranges.size()));
+  snprintf(buf, sizeof(buf), "%s:cu%d:dt%d:n%d:k%d:q%d:st%d:tus%lld:img%d", b->arch.c_str(),
+           b->cus, b->dtype, 8 << (k.log2n - 3), k.kind, k.qstep, int(k.staged) + 2 * k.kb,
+           (long long)(k.tu_end - k.tu_begin), bucket_images(b, k));
   return buf;
 }
+
+// Drop and rebuild the unified item lists (after a change of item size).
+hipError_t rebuild_unified(adct_batch* b);
 
 int cache_lookup(const std::string& key) {
   const char* path = getenv("ADCT_TUNE_CACHE");
@@ -699,6 +759,48 @@ void cache_store(const std::string& key, int value) {
 
 bool valid_bs(const Bucket& k, int bs) {
   return k.log2n == 3 ? (bs == 64 || bs == 256) : (bs == 128 || bs == 256);
+}
+
+hipError_t rebuild_unified(adct_batch* b) {
+  drop_graph(b);
+  for (auto& u : b->unified)
+    if (u.d_items) (void)hipFree(u.d_items);
+  if (b->d_ubuckets) (void)hipFree(b->d_ubuckets);
+  b->unified.clear();
+  b->d_ubuckets = nullptr;
+  return build_unified(b, b->pos);
+}
+
+bool has_small(const adct_batch* b) {
+  for (const auto& u : b->unified)
+    if (u.small) return true;
+  return false;
+}
+
+// Cache key and code of the small-bound launch's shape: groups per item for
+// 8x8 and 16x16 TUs, persistent form, resident workgroups per CU.
+std::string small_key(const adct_batch* b) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s:cu%d:dt%d:tus%lld:img%d:small", b->arch.c_str(), b->cus,
+           b->dtype, static_cast<long long>(b->n_tus), b->n_images);
+  return buf;
+}
+
+int encode_small(const adct_batch* b) {
+  return 1 + b->small_groups[0] + (b->small_groups[1] << 4) + (int(b->persistent) << 8) +
+         (b->wgs_per_cu << 12);
+}
+
+bool decode_small(adct_batch* b, int code) {
+  code -= 1;
+  const int g8 = code & 15, g16 = (code >> 4) & 15, pers = (code >> 8) & 1, wpc = code >> 12;
+  auto ok_g = [](int g) { return g == 1 || g == 2 || g == 4 || g == 8; };
+  if (!ok_g(g8) || !ok_g(g16) || wpc < 1 || wpc > 16) return false;
+  b->small_groups[0] = g8;
+  b->small_groups[1] = g16;
+  b->persistent = pers != 0;
+  b->wgs_per_cu = wpc;
+  return true;
 }
 
 }  // namespace
@@ -867,7 +969,13 @@ ADCT_API int adct_batch_create(const adct_image_desc_t* images, int n_images,
       if (valid_bs(k, cached)) k.bs = cached;
     e = build_items(b, k);
   }
-  if (e == hipSuccess) e = build_unified(b, pos);
+  b->pos = std::move(pos);
+  if (e == hipSuccess) e = build_unified(b, b->pos);
+  if (e == hipSuccess) {
+    // a cached choice of the small-bound launch's shape
+    const int cached = cache_lookup(small_key(b));
+    if (cached > 0 && decode_small(b, cached)) e = rebuild_unified(b);
+  }
   if (e != hipSuccess) {
     free_plan(b);
     return hip_fail(e, "batch: upload");
@@ -904,6 +1012,24 @@ ADCT_API int adct_batch_info(const adct_batch_t* b, int64_t* out) {
   }
   out[8] = unified_items;
   out[9] = small;
+  out[10] = b->small_groups[0];
+  out[11] = b->small_groups[1];
+  out[12] = b->persistent ? 1 : 0;
+  out[13] = b->wgs_per_cu;
+  return set_error(ADCT_OK, "");
+}
+
+ADCT_API int adct_batch_set_small_shape(adct_batch_t* b, int groups8, int groups16,
+                                        int persistent, int wgs_per_cu) {
+  if (b == nullptr) return set_error(ADCT_E_ARG, "batch: null plan");
+  auto ok_g = [](int g) { return g == 1 || g == 2 || g == 4 || g == 8; };
+  if (!ok_g(groups8) || !ok_g(groups16) || wgs_per_cu < 1 || wgs_per_cu > 16)
+    return set_error(ADCT_E_ARG, "batch: groups per item 1, 2, 4 or 8; 1..16 workgroups per CU");
+  b->small_groups[0] = groups8;
+  b->small_groups[1] = groups16;
+  b->persistent = persistent != 0;
+  b->wgs_per_cu = wgs_per_cu;
+  if (hipError_t e = rebuild_unified(b); e != hipSuccess) return hip_fail(e, "batch: items");
   return set_error(ADCT_OK, "");
 }
 
@@ -1015,12 +1141,72 @@ ADCT_API int adct_batch_tune(adct_batch_t* b, const void* d_src, void* d_dst, in
     if (chosen) chosen[nb] = best_bs;
     ++nb;
   }
+  // the small-bound unified launch: groups per item for 8x8 and 16x16 TUs
+  // (1, 2 or 4), then the persistent form at 4 or 8 resident workgroups per
+  // CU against the one-shot grid
+  if (e == hipSuccess && has_small(b)) {
+    const std::string key = small_key(b);
+    const int cached = cache_lookup(key);
+    if (cached > 0 && decode_small(b, cached)) {
+      e = rebuild_unified(b);
+    } else {
+      auto time_unified = [&](float* out) {
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = enqueue_run(b, d_src, d_dst, d_kept, d_scaled, d_sse, nullptr, ADCT_RUN_UNIFIED, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) t_min = std::min(t_min, ms);   // the first run warms up
+        }
+        *out = t_min;
+      };
+      float best = 1e30f;
+      int best_code = encode_small(b);
+      const int cands[3] = {1, 2, 4};
+      b->persistent = false;
+      for (int i8 = 0; i8 < 3 && e == hipSuccess; ++i8)
+        for (int i16 = 0; i16 < 3 && e == hipSuccess; ++i16) {
+          b->small_groups[0] = cands[i8];
+          b->small_groups[1] = cands[i16];
+          e = rebuild_unified(b);
+          float ms = 1e30f;
+          if (e == hipSuccess) time_unified(&ms);
+          if (ms < best) {
+            best = ms;
+            best_code = encode_small(b);
+          }
+        }
+      if (e == hipSuccess) {
+        decode_small(b, best_code);
+        e = rebuild_unified(b);
+      }
+      const int wpcs[2] = {4, 8};
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+        b->persistent = true;
+        b->wgs_per_cu = wpcs[w];
+        float ms = 1e30f;
+        time_unified(&ms);
+        if (ms < best) {
+          best = ms;
+          best_code = encode_small(b);
+        }
+      }
+      if (e == hipSuccess) {
+        decode_small(b, best_code);
+        cache_store(key, best_code);
+      }
+    }
+  }
   // the sequence a graph replays: the tuned per-bucket launches or the
   // unified launch, whichever is faster on these buffers
   if (e == hipSuccess) {
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s:dt%d:tus%lld:img%d:sequence", b->arch.c_str(), b->dtype,
-             static_cast<long long>(b->n_tus), b->n_images);
+    snprintf(buf, sizeof(buf), "%s:cu%d:dt%d:tus%lld:img%d:sequence", b->arch.c_str(), b->cus,
+             b->dtype, static_cast<long long>(b->n_tus), b->n_images);
     if (const int cached = cache_lookup(buf); cached == 1 || cached == 2) {
       b->prefer_unified = cached == 1;
     } else {

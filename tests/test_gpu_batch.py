@@ -155,3 +155,43 @@ def test_boundary_split_of_residual_frame():
     for i, d in enumerate(descs):
         assert np.array_equal(ragged.unpack_image(dst, d), want_recon[i])
         assert sse[i] == want_sse[i]
+
+
+@pytest.mark.parametrize("shape", [(1, 1, False, 8), (4, 4, False, 8), (2, 2, True, 8),
+                                   (1, 4, True, 4), (4, 1, True, 1)])
+def test_small_bound_shapes_agree_with_the_oracle(shape):
+    """Every shape of the row-per-thread unified launch (groups per item, the
+    persistent grid) gives the oracle's outputs for every TU."""
+    imgs, descs, tus, arena = make_set("u8", 9000, r_set=(1, 6, 10, 15, 21, 28, 36))
+    plan = adct.BatchPlan(descs, tus, torch.uint8)
+    plan.set_small_shape(*shape)
+    info = plan.info()
+    assert info["small_bound"] == 1
+    assert (info["small_groups8"], info["small_groups16"], info["persistent"],
+            info["wgs_per_cu"]) == (shape[0], shape[1], int(shape[2]), shape[3])
+    dst, kept, scaled, sse, psnr = run_plan(plan, arena, "unified")
+    want_kept, want_scaled, want_recon, want_sse = oracle_expect(imgs, descs, tus)
+    for t in range(len(tus)):
+        o = int(plan.tu_kept_offset[t])
+        assert np.array_equal(kept[o:o + len(want_kept[t])], want_kept[t]), t
+    for i, d in enumerate(descs):
+        assert np.array_equal(ragged.unpack_image(dst, d), want_recon[i]), i
+        assert sse[i] == want_sse[i]
+
+
+def test_tune_searches_the_small_bound_shape():
+    imgs, descs, tus, arena = make_set("u8", 9100, r_set=(1, 6, 10, 15, 21, 28, 36))
+    plan = adct.BatchPlan(descs, tus, torch.uint8)
+    base = run_plan(plan, arena, "unified")
+    src = torch.from_numpy(arena).to(DEV)
+    dst = torch.zeros_like(src)
+    kept = torch.zeros(plan.kept_words, dtype=torch.int32, device=DEV)
+    plan.tune(src, dst, kept)
+    info = plan.info()
+    assert info["small_groups8"] in (1, 2, 4) and info["small_groups16"] in (1, 2, 4)
+    assert info["persistent"] in (0, 1) and info["wgs_per_cu"] in (4, 8)
+    got = run_plan(plan, arena, "unified")
+    for a, b in zip(base, got):
+        assert np.array_equal(a, b)
+    with pytest.raises(adct.AdctError):
+        plan.set_small_shape(3, 2)
