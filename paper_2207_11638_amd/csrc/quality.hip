@@ -22,8 +22,10 @@
 // to the image's record.  Squares are split into their low and high 32-bit
 // halves, each summed in 64 bits, so every sum is exact for any int16 input.
 #include <algorithm>
+#include <type_traits>
 
 #include "jam_group.hpp"
+#include "tile8.hpp"
 
 namespace adct {
 namespace {
@@ -168,66 +170,89 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
   unsigned long long a2 = 0;
   long long tiles = 0;
 
-  GroupIO io{};
-  io.src = p.src;
-  io.pitch = p.g.pitch;
-  for (int64_t q = blockIdx.x; q < groups; q += p.wpi) {
-    const int ty = static_cast<int>(q / groups_x);
-    const int tx0 = static_cast<int>(q - static_cast<int64_t>(ty) * groups_x) * C::TPW;
-    const int nact = min(C::TPW, p.g.tiles_x - tx0);
-    io.active = k < nact;
-    io.tile_pix = static_cast<int64_t>(img) * p.g.image_stride +
-                  static_cast<int64_t>(ty) * N * p.g.pitch + static_cast<int64_t>(tx0 + k) * N;
-    RowWords<N, DT> x;
-    row_forward<KIND, N, DT, kBlock>(S, io, a_idx, k, x);
-    if (io.active) {   // pixel sums of this row, level-shifted for 8-bit input
-      if constexpr (DT == DT_U8) {
-        uint32_t sx = 0, sxx = 0;
+  // U tile groups per step, q0 + u wpi (u < U): their rows are all loaded
+  // before the first is transformed, so a workgroup keeps U row loads in
+  // flight (the walk covers the image's groups b, b + wpi, ... exactly once)
+  constexpr int U = N == 8 ? 4 : (N == 16 ? 2 : 1);
+  for (int64_t q0 = blockIdx.x; q0 < groups; q0 += static_cast<int64_t>(U) * p.wpi) {
+    RowWords<N, DT> xs[U];
+    int nacts[U];
 #pragma unroll
-        for (int d = 0; d < RowWords<N, DT>::W; ++d) {
-          sx = __builtin_amdgcn_udot4(x.w[d], 0x01010101u, sx, false);
-          sxx = __builtin_amdgcn_udot4(x.w[d], x.w[d], sxx, false);
-        }
-        // a = x - 128: sum a = sum x - 128 N, sum a^2 = sum x^2 - 256 sum x + 128^2 N
-        a1 += static_cast<long long>(sx) - 128 * N;
-        a2 += static_cast<unsigned long long>(sxx) + 16384ull * N - 256ull * sx;
-      } else {
-        int xv[N];
-        unpack_row<N, DT>(x, xv);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          a1 += xv[i];
-          a2 += static_cast<unsigned long long>(static_cast<long long>(xv[i]) * xv[i]);
-        }
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = q0 + static_cast<int64_t>(u) * p.wpi;
+      nacts[u] = 0;
+      int64_t pix = 0;
+      if (q < groups) {
+        const int ty = static_cast<int>(q / groups_x);
+        const int tx0 = static_cast<int>(q - static_cast<int64_t>(ty) * groups_x) * C::TPW;
+        nacts[u] = min(C::TPW, p.g.tiles_x - tx0);
+        pix = static_cast<int64_t>(img) * p.g.image_stride +
+              static_cast<int64_t>(ty) * N * p.g.pitch + static_cast<int64_t>(tx0 + k) * N;
       }
+      load_row<N, DT>(p.src, pix + static_cast<int64_t>(a_idx) * p.g.pitch, k < nacts[u], xs[u]);
     }
-    __syncthreads();
-    int c[N];
-    read_column<N, kBlock>(S, a_idx, k, c);
-    fwdN<KIND, N>(c);
-    if constexpr (DT == DT_U8)
-      if (a_idx == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
-    __syncthreads();
-    write_column_rows<N, kBlock>(S, a_idx, k, c);   // padded [k][v][u]
-    __syncthreads();
 #pragma unroll
-    for (int pq = 0; pq < PPT; ++pq) {
-      const int pos = p0 + pq * kBlock;
-      const int off = (pos / N) * C::CS + pos % N;
-      for (int kk = k0; kk < nact; kk += KSTEP) {
-        const int b = S[kk * C::TS + off];
-        s1[pq] += b;
-        if constexpr (SMALL) {
-          s2lo[pq] += static_cast<uint32_t>(__mul24(b, b));
+    for (int u = 0; u < U; ++u) {
+      const int nact = nacts[u];
+      if (nact == 0) break;   // uniform: the walk's last groups
+      const RowWords<N, DT>& x = xs[u];
+      {   // row transform into the column-major exchange area
+        int a[N];
+        unpack_row<N, DT>(x, a);
+        fwdN<KIND, N>(a);
+#pragma unroll
+        for (int j = 0; j < N; ++j) S[k * C::TS + j * C::CS + a_idx] = a[j];
+      }
+      if (k < nact) {   // pixel sums of this row, level-shifted for 8-bit input
+        if constexpr (DT == DT_U8) {
+          uint32_t sx = 0, sxx = 0;
+#pragma unroll
+          for (int d = 0; d < RowWords<N, DT>::W; ++d) {
+            sx = __builtin_amdgcn_udot4(x.w[d], 0x01010101u, sx, false);
+            sxx = __builtin_amdgcn_udot4(x.w[d], x.w[d], sxx, false);
+          }
+          // a = x - 128: sum a = sum x - 128 N, sum a^2 = sum x^2 - 256 sum x + 128^2 N
+          a1 += static_cast<long long>(sx) - 128 * N;
+          a2 += static_cast<unsigned long long>(sxx) + 16384ull * N - 256ull * sx;
         } else {
-          const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
-          s2lo[pq] += static_cast<uint32_t>(sq);
-          s2hi[pq] += sq >> 32;
+          int xv[N];
+          unpack_row<N, DT>(x, xv);
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            a1 += xv[i];
+            a2 += static_cast<unsigned long long>(static_cast<long long>(xv[i]) * xv[i]);
+          }
         }
       }
+      __syncthreads();
+      int c[N];
+      read_column<N, kBlock>(S, a_idx, k, c);
+      fwdN<KIND, N>(c);
+      if constexpr (DT == DT_U8)
+        if (a_idx == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
+      __syncthreads();
+      write_column_rows<N, kBlock>(S, a_idx, k, c);   // padded [k][v][u]
+      __syncthreads();
+#pragma unroll
+      for (int pq = 0; pq < PPT; ++pq) {
+        const int pos = p0 + pq * kBlock;
+        const int off = (pos / N) * C::CS + pos % N;
+        for (int kk = k0; kk < nact; kk += KSTEP) {
+          const int b = S[kk * C::TS + off];
+          s1[pq] += b;
+          if constexpr (SMALL) {
+            s2lo[pq] += static_cast<uint32_t>(__mul24(b, b));
+          } else {
+            const unsigned long long sq =
+                static_cast<unsigned long long>(static_cast<long long>(b) * b);
+            s2lo[pq] += static_cast<uint32_t>(sq);
+            s2hi[pq] += sq >> 32;
+          }
+        }
+      }
+      tiles += nact;
+      __syncthreads();   // S is rewritten by the next group
     }
-    tiles += nact;
-    __syncthreads();   // S is rewritten by the next group
   }
 
   unsigned long long* rec = p.mom + static_cast<int64_t>(img) * (3 * NN + 4);
@@ -282,6 +307,106 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
     atomicAdd(rec + 3 * NN + 1, static_cast<unsigned long long>(tiles) * NN);
     if (b1 != 0) atomicAdd(rec + 3 * NN + 2, static_cast<unsigned long long>(b1));
     if (b2 != 0) atomicAdd(rec + 3 * NN + 3, b2);
+  }
+}
+
+// 8 x 8 tiles: one thread per tile, one wave per workgroup (as the fused
+// 8-point kernels).  A wave walks the 64-tile groups q = b, b + wpi, ... of
+// its image; for each it transforms its tiles in registers, writes the 64
+// coefficients of each tile to LDS, and lane p then adds position p of all
+// the group's tiles to its running sums (32-bit within a group where the
+// bound allows, 64-bit across groups).  One set of atomics per wave at the end.
+template <int KIND, int DT>
+__global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
+  using namespace t8;
+  constexpr int NN = kN * kN;
+  constexpr int RS = NN + 1;
+  constexpr bool SMALL = small_squares<KIND, 8, DT>();
+  // 8-bit input where every |b| < 2^15: the exchange holds 16-bit words (half
+  // the LDS of a wave, twice the waves per CU)
+  using Word = typename std::conditional<SMALL, short, int>::type;
+  __shared__ Word lds[kWave * RS];
+  const int img = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int groups_x = (p.g.tiles_x + kWave - 1) / kWave;
+  const int64_t groups = static_cast<int64_t>(groups_x) * p.g.tiles_y;
+  long long s1 = 0, a1 = 0;
+  unsigned long long s2lo = 0, s2hi = 0, a2 = 0;
+  long long tiles = 0;
+  for (int64_t q = blockIdx.x; q < groups; q += p.wpi) {
+    const int ty = static_cast<int>(q / groups_x);
+    const int gx = static_cast<int>(q - static_cast<int64_t>(ty) * groups_x);
+    const WaveTiles w = wave_tiles_at(p.g, gx, ty, img);
+    Raw<DT> raw;
+    load_raw<DT>(p.src, w.pix, p.g.pitch, w.active, raw);
+    if (w.active) {   // pixel sums of the tile, level-shifted for 8-bit input
+      if constexpr (DT == DT_U8) {
+        uint32_t sx = 0, sxx = 0;
+#pragma unroll
+        for (int i = 0; i < kN; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            sx = __builtin_amdgcn_udot4(raw.w[i][j], 0x01010101u, sx, false);
+            sxx = __builtin_amdgcn_udot4(raw.w[i][j], raw.w[i][j], sxx, false);
+          }
+        a1 += static_cast<long long>(sx) - 128 * NN;
+        a2 += static_cast<unsigned long long>(sxx) + 16384ull * NN - 256ull * sx;
+      }
+    }
+    int a[kN][kN];
+    unpack<DT>(raw, a);
+    if constexpr (DT != DT_U8) {
+      if (w.active) {
+#pragma unroll
+        for (int i = 0; i < kN; ++i)
+#pragma unroll
+          for (int j = 0; j < kN; ++j) {
+            a1 += a[i][j];
+            a2 += static_cast<unsigned long long>(static_cast<long long>(a[i][j]) * a[i][j]);
+          }
+      }
+    }
+    forward2d<KIND>(a);
+    if constexpr (DT == DT_U8) a[0][0] -= 128 * NN;
+#pragma unroll
+    for (int v = 0; v < kN; ++v)
+#pragma unroll
+      for (int u = 0; u < kN; ++u) lds[lane * RS + v * kN + u] = static_cast<Word>(a[v][u]);
+    __syncthreads();
+    // lane = coefficient position; tiles of the group one after the other.
+    // The group's sum stays in 32 bits (64 |b| < 2^21); squares go straight
+    // to 64 bits (64 of them can reach 2^32: an all-zero image has |DC| = 2^13).
+    int g1 = 0;
+    for (int t = 0; t < w.nact; ++t) {
+      const int b = static_cast<int>(lds[t * RS + lane]);
+      if constexpr (SMALL) {
+        g1 += b;
+        s2lo += static_cast<uint32_t>(__mul24(b, b));   // |b| < 2^15: b^2 < 2^30
+      } else {
+        s1 += b;
+        const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
+        s2lo += static_cast<uint32_t>(sq);
+        s2hi += sq >> 32;
+      }
+    }
+    if constexpr (SMALL) s1 += g1;
+    tiles += w.nact;
+    __syncthreads();   // the next group rewrites the LDS area
+  }
+  unsigned long long* rec = p.mom + static_cast<int64_t>(img) * (3 * NN + 4);
+  if (s1 != 0) atomicAdd(rec + lane, static_cast<unsigned long long>(s1));
+  if (s2lo != 0) atomicAdd(rec + NN + lane, s2lo);
+  if (s2hi != 0) atomicAdd(rec + 2 * NN + lane, s2hi);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a1 += __shfl_xor(a1, off, 64);
+    a2 += __shfl_xor(a2, off, 64);
+  }
+  if (lane == 0 && tiles > 0) {
+    atomicAdd(rec + 3 * NN, static_cast<unsigned long long>(tiles));
+    atomicAdd(rec + 3 * NN + 1, static_cast<unsigned long long>(tiles) * NN);
+    if (a1 != 0) atomicAdd(rec + 3 * NN + 2, static_cast<unsigned long long>(a1));
+    if (a2 != 0) atomicAdd(rec + 3 * NN + 3, a2);
   }
 }
 
@@ -436,6 +561,29 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
   p.src = src;
   p.g = g;
   p.mom = mom;
+  if (n == 8) {
+    // one-wave workgroups, about 32768 in all (several times what the chip
+    // holds at once, so the last ones to start leave little tail), each
+    // walking 64-tile groups of its image
+    const int64_t groups8 = static_cast<int64_t>((g.tiles_x + 63) / 64) * g.tiles_y;
+    int64_t wpi8 = (32768 + g.batch - 1) / g.batch;
+    wpi8 = std::max<int64_t>(1, std::min<int64_t>(wpi8, groups8));
+    p.wpi = static_cast<int>(wpi8);
+    const dim3 grid8(p.wpi, g.batch);
+    auto go = [&](auto kind_tag) {
+      constexpr int K = decltype(kind_tag)::value;
+      if (dtype == DT_U8) moments8_kernel<K, DT_U8><<<grid8, t8::kWave, 0, s>>>(p);
+      else moments8_kernel<K, DT_I16><<<grid8, t8::kWave, 0, s>>>(p);
+    };
+    switch (kind) {
+      case KIND_SIGN: go(std::integral_constant<int, KIND_SIGN>{}); break;
+      case KIND_ROUND: go(std::integral_constant<int, KIND_ROUND>{}); break;
+      case KIND_WHT: go(std::integral_constant<int, KIND_WHT>{}); break;
+      case KIND_SDCT: go(std::integral_constant<int, KIND_SDCT>{}); break;
+      default: go(std::integral_constant<int, KIND_HT>{}); break;
+    }
+    return hipGetLastError();
+  }
   const int tpw = kBlock / n;
   const int64_t groups = static_cast<int64_t>((g.tiles_x + tpw - 1) / tpw) * g.tiles_y;
   // about 2048 workgroups in all (8 per CU), each walking its image's groups
@@ -444,9 +592,6 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
   if (wpi > groups) wpi = groups;
   if (wpi < 1) wpi = 1;
   p.wpi = static_cast<int>(wpi);
-  if (kind == KIND_WHT) return launch_moments_typed<KIND_WHT, 8>(dtype, p, s);
-  if (kind == KIND_SDCT) return launch_moments_typed<KIND_SDCT, 8>(dtype, p, s);
-  if (kind == KIND_HT) return launch_moments_typed<KIND_HT, 8>(dtype, p, s);
   if (n == 64) {   // 8-bit input only (the host refuses the rest)
     const dim3 grid(p.wpi, p.g.batch);
     if (kind == KIND_SIGN) moments_kernel<KIND_SIGN, 64, DT_U8><<<grid, kBlock, 0, s>>>(p);
@@ -454,11 +599,9 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
     return hipGetLastError();
   }
   if (kind == KIND_SIGN) {
-    if (n == 8) return launch_moments_typed<KIND_SIGN, 8>(dtype, p, s);
     if (n == 16) return launch_moments_typed<KIND_SIGN, 16>(dtype, p, s);
     return launch_moments_typed<KIND_SIGN, 32>(dtype, p, s);
   }
-  if (n == 8) return launch_moments_typed<KIND_ROUND, 8>(dtype, p, s);
   if (n == 16) return launch_moments_typed<KIND_ROUND, 16>(dtype, p, s);
   return launch_moments_typed<KIND_ROUND, 32>(dtype, p, s);
 }

@@ -83,6 +83,20 @@ def test_moments_full_int16_range(n):
         assert record_matches(mom[0], P.coefficient_moments(img, kind, n), n)
 
 
+@pytest.mark.parametrize("kind", M.KINDS + M.COMPARISON_KINDS)
+def test_moments_extreme_u8_full_groups(kind):
+    """All-0 and all-255 images whose tile rows hold full 64-tile groups: at
+    the DC position 64 tiles of |b| = 128 * 64 square to 2^32 in sum, which
+    a 32-bit accumulator would wrap."""
+    w = 8 * 64 * 3 + 24
+    imgs = [np.zeros((16, w), np.uint8), np.full((16, w), 255, np.uint8)]
+    yy, xx = np.indices((16, w))
+    imgs.append(((yy + xx) % 2 * 255).astype(np.uint8))
+    mom = host(adct.moments(to_dev(np.stack(imgs)), kind, 8))
+    for i, im in enumerate(imgs):
+        assert record_matches(mom[i], P.coefficient_moments(im, kind, 8), 8), (i, kind)
+
+
 def test_moments_accumulate_over_calls():
     img = synth.ar1_image(64, 256, rho=0.95, seed=11)
     x = to_dev(img)
