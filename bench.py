@@ -379,7 +379,9 @@ def run_c1(args):
             "workload": c4["workload"], "p50_ms": r4["main"]["p50_ms"],
             "p99_ms": r4["main"]["p99_ms"], "max_ms": r4["main"]["max_ms"],
             "served_gpixel_s": r4["main"]["served_gpixel_s"],
-            "mean_batch": r4["main"]["mean_batch"], "parity_sample": r4["parity_sample"]}
+            "mean_batch": r4["main"]["mean_batch"],
+            "host_wait_ms": r4["main"]["host_wait_ms"], "device_ms": r4["main"]["device_ms"],
+            "slowest": r4["main"]["slowest"], "parity_sample": r4["parity_sample"]}
     print(json.dumps(line), flush=True)
 
 
@@ -1195,23 +1197,34 @@ def gpu_c4(args, d, sweep):
         recs["dtype"] = adct.ADCT_U8
         recs["height"] = sizes[j, 0]
         recs["width"] = sizes[j, 1]
+        return recs
+
+    def check_records(trace_, recs, sample_every):
+        """The sampled requests again, with pinned host buffers that receive
+        their kept coefficients and reconstruction.  They run as a separate
+        replay: a copy into host memory issued from the loop thread has
+        blocked that thread for 6-10 ms about once per trace, which would
+        stall the timed requests arriving meanwhile."""
+        picks = list(range(0, len(trace_), sample_every))
+        sub_ = recs[picks].copy()
+        j = np.arange(len(trace_)) % pool_n
         checks = []
-        for i in range(0, m, sample_every) if sample_every else ():
+        for k, i in enumerate(picks):
             t = trace_[i]
             h, w = (int(v) for v in sizes[j[i]])
             h_kept = torch.empty((h // t["n"]) * (w // t["n"]) * t["r"],
                                  dtype=torch.int32).pin_memory()
             h_recon = torch.empty((h, w), dtype=torch.uint8).pin_memory()
-            recs["h_kept"][i] = h_kept.data_ptr()
-            recs["h_recon"][i] = h_recon.data_ptr()
+            sub_["h_kept"][k] = h_kept.data_ptr()
+            sub_["h_recon"][k] = h_recon.data_ptr()
             checks.append((i, int(j[i]), h_kept, h_recon))
-        return recs, checks
+        return sub_, checks
 
     def replay(trace_, rate, sample_every=0):
-        recs, checks = build(trace_, sample_every)
+        recs = build(trace_, sample_every)
         arrival_ms = np.array([t["t"] for t in trace_]) * 1e3
         srv = adct.Server(budget, max_inflight=2, max_batch=1024, stream=stream)
-        lat, batch, sse = srv.run_trace(recs, arrival_ms)
+        lat, batch, sse, launch = srv.run_trace(recs, arrival_ms, launch_times=True)
         st = srv.stats()
         srv.close()
         served_px = int(px[np.arange(len(trace_)) % pool_n].sum())
@@ -1225,13 +1238,36 @@ def gpu_c4(args, d, sweep):
                "batches": int(st["batches"]), "largest_batch": int(st["max_batch"]),
                "mean_batch": round(len(trace_) / max(1, st["batches"]), 2),
                "budget_waits": int(st["refused"])}
-        return res, checks, sse, lat
+        # where the time went: waiting on the host (arrival -> launch of the
+        # request's batch) and on the device (launch -> completion event)
+        host = launch - arrival_ms
+        dev = lat - host
+        res["host_wait_ms"] = {"p50": round(float(np.percentile(host, 50)), 3),
+                               "p99": round(float(np.percentile(host, 99)), 3),
+                               "max": round(float(np.max(host)), 3)}
+        res["device_ms"] = {"p50": round(float(np.percentile(dev, 50)), 3),
+                            "p99": round(float(np.percentile(dev, 99)), 3),
+                            "max": round(float(np.max(dev)), 3)}
+        checks = None
+        if sample_every:
+            # the check replay: sampled requests submitted at once, outputs
+            # copied to the host; its error energies must equal the timed ones
+            sub_, checks = check_records(trace_, recs, sample_every)
+            srv = adct.Server(budget, max_inflight=2, max_batch=1024, stream=stream)
+            _, _, sse_c = srv.run_trace(sub_, np.zeros(len(sub_)))
+            srv.close()
+            checks = [(i, jj, hk, hr, int(sse_c[k]), int(sse[i]))
+                      for k, (i, jj, hk, hr) in enumerate(checks)]
+        return res, checks, sse, lat, (host, dev, batch)
 
-    main_res, checks, sse, lat = replay(
+    main_res, checks, sse, lat, (host, dev, batch) = replay(
         trace, args.rate, sample_every=max(1, min(100, n_req // max(1, args.check_max))))
     slow = np.argsort(lat)[-3:][::-1]
     main_res["slowest"] = [{"request": int(i), "arrival_ms": round(trace[i]["t"] * 1e3, 3),
-                            "latency_ms": round(float(lat[i]), 3)} for i in slow]
+                            "latency_ms": round(float(lat[i]), 3),
+                            "host_wait_ms": round(float(host[i]), 3),
+                            "device_ms": round(float(dev[i]), 3), "batch": int(batch[i])}
+                           for i in slow]
     log(f"served {n_req} requests at {args.rate:.0f}/s: p50 {main_res['p50_ms']} ms, "
         f"p99 {main_res['p99_ms']} ms, max {main_res['max_ms']} ms, "
         f"{main_res['served_gpixel_s']} Gpx/s, {main_res['batches']} batches; slowest "
@@ -1241,14 +1277,15 @@ def gpu_c4(args, d, sweep):
     if not args.no_check:
         from concurrent.futures import ThreadPoolExecutor
         tasks = []
-        for i, j, hk, hr in checks:
+        same = all(sc == st for _, _, _, _, sc, st in checks)
+        for i, j, hk, hr, sc, _ in checks:
             t = trace[i]
             img = arena[int(offsets[j]):int(offsets[j] + px[j])].reshape(int(sizes[j, 0]),
                                                                           int(sizes[j, 1]))
             tasks.append((img, t["transform"], t["n"], t["r"], hk.numpy().copy(),
-                          hr.numpy().copy(), int(sse[i])))
+                          hr.numpy().copy(), sc))
         with ThreadPoolExecutor(host_workers(args.gen_workers)) as ex:
-            good = list(ex.map(_c4_check, tasks))
+            good = list(ex.map(_c4_check, tasks)) + [same]
         check = "ok" if all(good) else f"{len(good) - sum(good)} of {len(good)} mismatches"
         log(f"oracle check of {len(tasks)} sampled requests ({100 * len(tasks) / n_req:.1f} %): "
             f"{check}")
@@ -1257,7 +1294,7 @@ def gpu_c4(args, d, sweep):
     plain = None
     if sweep:
         for rate, tr in d["sweep"]:
-            res, _, _, _ = replay(tr, rate)
+            res, _, _, _, _ = replay(tr, rate)
             sweep_res.append(res)
             log(f"sweep {rate:.0f}/s: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms, "
                 f"served {res['served_gpixel_s']} of offered {res['offered_gpixel_s']} Gpx/s, "

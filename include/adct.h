@@ -490,6 +490,8 @@ typedef struct {
   int64_t batch;           /* sequence number of the batch it ran in (0, 1, ...) */
   uint64_t sse;            /* error energy of its reconstruction                 */
   double done_ms;          /* completion time on the server clock                */
+  double launch_ms;        /* host time (server clock) of the flush that launched */
+                           /*   the request's batch                               */
   const int32_t* d_kept;   /* outputs in the arena, valid until the next poll:   */
   const float* d_scaled;   /*   kept [tiles][r] (zig-zag order), scaled (or NULL), */
   const void* d_recon;     /*   reconstruction (height rows of pitch pixels)     */
@@ -538,11 +540,14 @@ ADCT_API double adct_server_clock_ms(const adct_server_t* server);
  * launched through the pipeline of adct_compress (section 5.1); the call
  * returns when every request has completed.
  * latency_ms[i] = completion - arrival, batch_of[i] = its batch, sse[i] = its
- * error energy (any of the three may be NULL).  A request that fails
- * validation gets latency NaN and batch -1.  The server must be idle. */
+ * error energy, launch_ms[i] = host time of the flush that launched it,
+ * milliseconds after the start (launch_ms - arrival is the time it waited on
+ * the host, latency - that the time on the device); any of the four may be
+ * NULL.  A request that fails validation gets latency and launch time NaN
+ * and batch -1.  The server must be idle. */
 ADCT_API int adct_server_run_trace(adct_server_t* server, const adct_request_t* requests,
                                    const double* arrival_ms, int64_t n, double* latency_ms,
-                                   int64_t* batch_of, uint64_t* sse);
+                                   int64_t* batch_of, uint64_t* sse, double* launch_ms);
 
 #ifdef __cplusplus
 }

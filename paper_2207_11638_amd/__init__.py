@@ -426,7 +426,8 @@ REQUEST = np.dtype([("d_src", np.uint64), ("h_kept", np.uint64), ("h_scaled", np
                     ("n", np.int32), ("r", np.int32), ("qstep", np.int32), ("dtype", np.int32),
                     ("height", np.int32), ("width", np.int32), ("want_scaled", np.int32)])
 COMPLETION = np.dtype([("tag", np.int64), ("batch", np.int64), ("sse", np.uint64),
-                       ("done_ms", np.float64), ("d_kept", np.uint64), ("d_scaled", np.uint64),
+                       ("done_ms", np.float64), ("launch_ms", np.float64), ("d_kept", np.uint64),
+                       ("d_scaled", np.uint64),
                        ("d_recon", np.uint64)])
 
 
@@ -509,15 +510,18 @@ class Server:
     def clock_ms(self) -> float:
         return float(_lib.load().adct_server_clock_ms(self._h))
 
-    def run_trace(self, requests, arrival_ms):
+    def run_trace(self, requests, arrival_ms, launch_times: bool = False):
         """Replay an arrival trace in real time (native loop); returns
-        (latency_ms, batch_of, sse) arrays."""
+        (latency_ms, batch_of, sse) arrays, and launch_ms (host time of each
+        request's launch after the start) as a fourth when launch_times."""
         reqs = np.ascontiguousarray(requests, dtype=REQUEST)
         arr = np.ascontiguousarray(arrival_ms, dtype=np.float64)
         lat = np.zeros(len(reqs), dtype=np.float64)
         bat = np.zeros(len(reqs), dtype=np.int64)
         sse = np.zeros(len(reqs), dtype=np.uint64)
+        launch = np.zeros(len(reqs), dtype=np.float64)
         _lib.check(_lib.load().adct_server_run_trace(self._h, reqs.ctypes.data, arr.ctypes.data,
                                                      len(reqs), lat.ctypes.data,
-                                                     bat.ctypes.data, sse.ctypes.data))
-        return lat, bat, sse
+                                                     bat.ctypes.data, sse.ctypes.data,
+                                                     launch.ctypes.data))
+        return (lat, bat, sse, launch) if launch_times else (lat, bat, sse)

@@ -59,7 +59,7 @@ _SIGNATURES = {
     "adct_server_poll": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "adct_server_stats": ([_vp, _vp], _i32),
     "adct_server_clock_ms": ([_vp], C.c_double),
-    "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp], _i32),
+    "adct_server_run_trace": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp], _i32),
 }
 
 ADCT_BASIS_ROWS, ADCT_BASIS_COLS = 0, 1

@@ -57,26 +57,65 @@ inline int groups_per_wg(int groups_x, int64_t rows) {
   return gpw < 1 ? 1 : gpw;
 }
 
+// Sum of v over the 64 lanes of a wave (every lane active), as a uniform
+// value.  Data-parallel-primitive steps: shifts right by 1, 2, 4 and 8 within
+// each row of 16 lanes leave every row's sum in its lane 15; the broadcast of
+// lane 15 into the next row and of lane 31 into rows 2 and 3 then gathers the
+// four row sums in lane 63.  Lanes whose source lies outside the row (or in a
+// row the step does not write) add zero.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Sum e over the BS threads of a workgroup and add it to *sse with one
 // atomic (none when the sum is zero).  red: BS / 64 words of LDS (unused for
-// a single wave).  Every thread of the workgroup calls it.
+// a single wave).  Every thread of the workgroup calls it, with every lane of
+// its wave active.  Each e must be below 2^48 (the largest per-thread error
+// energy of the kernels is below 2^41): its low 24 and high 24 bits are summed
+// over the wave as two 32-bit values (64 terms below 2^24 each).
 template <int BS>
 __device__ __forceinline__ void block_add_sse(unsigned long long* sse, unsigned long long e,
                                               unsigned long long* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  const uint32_t lo = wave_sum_u32(static_cast<uint32_t>(e) & 0xffffffu);
+  const uint32_t hi = wave_sum_u32(static_cast<uint32_t>(e >> 24));
+  const unsigned long long w = static_cast<unsigned long long>(lo) +
+                               (static_cast<unsigned long long>(hi) << 24);
   if constexpr (BS == 64) {
-    if (threadIdx.x == 0 && e != 0) atomicAdd(sse, e);
+    if (threadIdx.x == 0 && w != 0) atomicAdd(sse, w);
   } else {
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long sum = 0;
 #pragma unroll
-      for (int w = 0; w < BS / 64; ++w) sum += red[w];
+      for (int i = 0; i < BS / 64; ++i) sum += red[i];
       if (sum != 0) atomicAdd(sse, sum);
     }
   }
+}
+
+// Quantiser multiplier MQ (2^24 fixed point) as the float64 m = MQ / 2^24
+// (exact).
+__device__ __forceinline__ double quant_mult(int32_t mq) {
+  return static_cast<double>(mq) * 0x1p-24;
+}
+
+// Quantisation level sign(b) floor(|b| MQ / 2^24 + 1/2), evaluated in
+// float64 as the truncation toward zero of sign(b) (|b| m + 1/2): |b| MQ <
+// 2^47, so |b| m + 1/2 is exact (a numerator below 2^48 over 2^24) and the
+// fused multiply-add rounds nothing; truncating the non-negative value
+// floors it.  Four full-rate instructions (convert, multiply-add with |b| as
+// a source modifier, sign copy, convert), where the 64-bit integer product
+// takes a quarter-rate multiply and a sign fix-up.
+__device__ __forceinline__ int quantise_level(int b, double m) {
+  const double x = static_cast<double>(b);
+  return static_cast<int>(__builtin_copysign(__builtin_fma(__builtin_fabs(x), m, 0.5), x));
 }
 
 enum class Mode : int { Compress = 0, Forward = 1, Inverse = 2, Decompress = 3 };

@@ -138,7 +138,7 @@ __device__ __forceinline__ void item_jam(const Outs& o, const BItem& it, const T
   constexpr int esize = DT == DT_U8 ? 1 : 2;
   using C = jam::Cfg<N, BS>;
   const BImage im = o.imgs[it.image];
-  jam::load_tables<N, BS>(sh, t, min(im.r, N * N));
+  jam::load_tables<KIND, N, BS, KB>(sh, t, min(im.r, N * N));
   const int k = threadIdx.x % C::TPW;
   jam::GroupIO io;
   io.src = offset_px(o.src, im.src_off, esize);
@@ -310,7 +310,7 @@ __device__ __forceinline__ void item_rows(const Outs& o, const BItem& it, const 
   using C = jam::Cfg<N, BS, KB>;
   const BImage im = o.imgs[it.image];
   const int r = min(im.r, N * N);
-  jam::load_tables<N, BS>(sh, t, r);
+  jam::load_tables<KIND, N, BS, KB>(sh, t, r);
   const int k = threadIdx.x % C::TPW;
   jam::GroupIO io;
   io.src = offset_px(o.src, im.src_off, esize);

@@ -345,18 +345,75 @@ ADCT_HD int round_shift_u8(int z) {
 }
 
 #if defined(__HIPCC__) || defined(__HIP__)
+// Four results of round_shift_u8<S> packed into one word, byte b from z_b.
+// Each clipped dividend holds its result in bits S .. S + 7 (byte 1 for
+// S = 8, byte 0 after the shift otherwise); two byte permutes and an or
+// gather the four bytes.
+template <int S>
+__device__ __forceinline__ uint32_t pack_round_u8(int z0, int z1, int z2, int z3) {
+  const auto clip = [](int z) -> uint32_t {
+    const int t = z + (1 << (S - 1)) + (128 << S) + (z >> 31);
+    const int c = t < 0 ? 0 : (t > (256 << S) - 1 ? (256 << S) - 1 : t);
+    return S == 8 ? static_cast<uint32_t>(c) : static_cast<uint32_t>(c) >> S;
+  };
+  constexpr uint32_t B = S == 8 ? 1u : 0u;   // byte holding the result
+  const uint32_t lo = __builtin_amdgcn_perm(clip(z1), clip(z0), 0x0c0c0000u | ((4u + B) << 8) | B);
+  const uint32_t hi = __builtin_amdgcn_perm(clip(z3), clip(z2), ((4u + B) << 24) | (B << 16) | 0x0c0cu);
+  return lo | hi;
+}
+
+// Pointers into device memory, typed as the global address space.  Pixel
+// and output pointers reach some kernels through tables in device memory
+// (the serving kernels' request records), where the compiler cannot tell
+// their address space and would emit flat accesses, which also count
+// against the LDS wait counter; the shared load and store helpers go through
+// these typed pointers, so every kernel gets global loads and stores.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+
+// Loads and stores of the HIP vector types through global pointers (as
+// native vectors: the class types have no assignment from the global
+// address space).
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint2 ld_global(const uint2* p) {
+  const u32x2_t v = *to_global(reinterpret_cast<const u32x2_t*>(p));
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_global(const uint4* p) {
+  const u32x4_t v = *to_global(reinterpret_cast<const u32x4_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_global(uint32_t* p, uint32_t v) { *to_global(p) = v; }
+__device__ __forceinline__ void st_global(uint2* p, uint2 v) {
+  *to_global(reinterpret_cast<u32x2_t*>(p)) = u32x2_t{v.x, v.y};
+}
+__device__ __forceinline__ void st_global(uint4* p, uint4 v) {
+  *to_global(reinterpret_cast<u32x4_t*>(p)) = u32x4_t{v.x, v.y, v.z, v.w};
+}
+
 // Streaming stores: every output word is written once and not read again by
 // the kernel, so the stores carry the non-temporal hint.
-__device__ __forceinline__ void st_stream(uint32_t* p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(uint32_t* p, uint32_t v) {
+  __builtin_nontemporal_store(v, to_global(p));
+}
 __device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
-  __builtin_nontemporal_store(v.x, &p->x);
-  __builtin_nontemporal_store(v.y, &p->y);
+  const gptr<uint32_t> g = to_global(reinterpret_cast<uint32_t*>(p));
+  __builtin_nontemporal_store(v.x, g);
+  __builtin_nontemporal_store(v.y, g + 1);
 }
 __device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
-  __builtin_nontemporal_store(v.x, &p->x);
-  __builtin_nontemporal_store(v.y, &p->y);
-  __builtin_nontemporal_store(v.z, &p->z);
-  __builtin_nontemporal_store(v.w, &p->w);
+  const gptr<uint32_t> g = to_global(reinterpret_cast<uint32_t*>(p));
+  __builtin_nontemporal_store(v.x, g);
+  __builtin_nontemporal_store(v.y, g + 1);
+  __builtin_nontemporal_store(v.z, g + 2);
+  __builtin_nontemporal_store(v.w, g + 3);
 }
 
 // Non-temporal store when NT (whole lines written by one wave: the data is
@@ -365,7 +422,7 @@ __device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
 template <bool NT, typename T>
 __device__ __forceinline__ void st_pix(T* p, T v) {
   if constexpr (NT) st_stream(p, v);
-  else *p = v;
+  else st_global(p, v);
 }
 #endif
 

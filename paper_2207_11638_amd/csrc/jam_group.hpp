@@ -70,41 +70,66 @@ struct Shared {
   int32_t zz[N * N];
 };
 
-// Inverse zig-zag scan of an N x N block: entry p is (v << 8) | u of the
-// coefficient at scan position p, built at compile time from zz_pos.
+// Zig-zag words of one (transform, N): entry p holds the word offset
+// v (N+1) + u, in the padded [v][u] layout, of the coefficient at scan
+// position p (low 16 bits) and its class-table entry cls[v] * 4 + cls[u]
+// (high bits).  Built at compile time from the row classes of the forward
+// butterfly, the numbering the host tables use.
 template <int N>
-struct ZigzagInv {
-  uint16_t vu[N * N];
+struct ZigzagWords {
+  int32_t w[N * N];
 };
 
-template <int N>
-constexpr ZigzagInv<N> make_zigzag_inv() {
-  ZigzagInv<N> z{};
+template <int KIND, int N>
+constexpr ZigzagWords<N> make_zigzag_words() {
+  const RowClasses<N> rc = row_classes<KIND, N>();
+  ZigzagWords<N> z{};
   for (int v = 0; v < N; ++v)
-    for (int u = 0; u < N; ++u) z.vu[zz_pos(N, v, u)] = static_cast<uint16_t>((v << 8) | u);
+    for (int u = 0; u < N; ++u)
+      z.w[zz_pos(N, v, u)] = (v * (N + 1) + u) | ((rc.cls[v] * 4 + rc.cls[u]) << 16);
   return z;
 }
 
-static __constant__ ZigzagInv<8> kZigzagInv8 = make_zigzag_inv<8>();
-static __constant__ ZigzagInv<16> kZigzagInv16 = make_zigzag_inv<16>();
-static __constant__ ZigzagInv<32> kZigzagInv32 = make_zigzag_inv<32>();
-static __constant__ ZigzagInv<64> kZigzagInv64 = make_zigzag_inv<64>();
+template <int KIND, int N>
+static __constant__ ZigzagWords<N> kZigzagWords = make_zigzag_words<KIND, N>();
 
-template <int N>
-__device__ __forceinline__ int zigzag_inv(int p) {
-  if constexpr (N == 8) return kZigzagInv8.vu[p];
-  else if constexpr (N == 16) return kZigzagInv16.vu[p];
-  else if constexpr (N == 32) return kZigzagInv32.vu[p];
-  else return kZigzagInv64.vu[p];
+// Kept rows of column u < 8 when the first r <= 64 zig-zag positions of an
+// 8 x 8 block are retained (the zig-zag prefix keeps rows 0 .. c[r][u] - 1).
+// The first eight anti-diagonals (positions below 36) are scanned in the
+// same order for every N >= 8, so for r <= 36 the same counts hold for the
+// first eight columns of any N x N block.
+struct KeepRows8 {
+  uint8_t c[65][8];
+};
+
+constexpr KeepRows8 make_keep_rows8() {
+  KeepRows8 k{};
+  for (int r = 0; r <= 64; ++r)
+    for (int u = 0; u < 8; ++u) {
+      int c = 0;
+      while (c < 8 && zz_pos(8, c, u) < r) ++c;
+      k.c[r][u] = static_cast<uint8_t>(c);
+    }
+  return k;
 }
 
-// Fill the tables of one workgroup.  Thread p < r writes zig-zag entry p from
-// the inverse scan; thread u < N counts the kept rows of column u by binary
-// lifting (zz_pos(N, v, u) grows with v, so the kept rows are a prefix).
-// The tables depend on r and on the row classes of `t` only, not on LDS, so
-// no barrier is needed before this.  The caller synchronises before the
-// first use.
-template <int N, int BS>
+static __constant__ KeepRows8 kKeepRows8 = make_keep_rows8();
+
+// Whether a group of N x N tiles with kept bound KB reads its kept-row counts
+// from kKeepRows8 (8 x 8 tiles, or a bound of 4 or 8 columns: r <= 36) rather
+// than from the workgroup's tables.
+template <int N, int KB>
+constexpr bool keep_from_table() {
+  return N == 8 || KB < N;
+}
+
+// Fill the tables of one workgroup.  Thread p < r copies zig-zag word p;
+// where the kept-row counts are needed from LDS (keep_from_table false),
+// thread u < N counts the kept rows of column u by binary lifting (zz_pos(N,
+// v, u) grows with v, so the kept rows are a prefix).  The tables depend on
+// r and on the row classes of `t` only, not on LDS, so no barrier is needed
+// before this.  The caller synchronises before the first use.
+template <int KIND, int N, int BS, int KB = N>
 __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int r) {
   const int i = threadIdx.x;
   if (i < 16) {
@@ -114,20 +139,18 @@ __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int 
   }
   if (i < N) {
     sh.cls[i] = t.cls[i];
-    int cnt = 0;   // largest cnt with zz_pos(N, cnt - 1, i) < r, by binary lifting
+    if constexpr (!keep_from_table<N, KB>()) {
+      int cnt = 0;   // largest cnt with zz_pos(N, cnt - 1, i) < r, by binary lifting
 #pragma unroll
-    for (int step = N; step > 0; step >>= 1)
-      if (cnt + step <= N && zz_pos(N, cnt + step - 1, i) < r) cnt += step;
-    sh.cnt[i] = cnt;
+      for (int step = N; step > 0; step >>= 1)
+        if (cnt + step <= N && zz_pos(N, cnt + step - 1, i) < r) cnt += step;
+      sh.cnt[i] = cnt;
+    }
   }
 #pragma unroll
   for (int q = 0; q < (N * N + BS - 1) / BS; ++q) {
     const int p = i + q * BS;
-    if (p < r) {
-      const int vu = zigzag_inv<N>(p);
-      const int v = vu >> 8, u = vu & 0xff;
-      sh.zz[p] = (v * (N + 1) + u) | ((t.cls[v] * 4 + t.cls[u]) << 16);
-    }
+    if (p < r) sh.zz[p] = kZigzagWords<KIND, N>.w[p];
   }
 }
 
@@ -164,7 +187,7 @@ __device__ __forceinline__ void load_row(const void* src, int64_t off, bool acti
   if constexpr (RowWords<N, DT>::W == 2) {   // 8 uint8 pixels
     uint2 w = make_uint2(fill, fill);
     if (active)
-      w = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(src) + off);
+      w = ld_global(reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(src) + off));
     rw.w[0] = w.x;
     rw.w[1] = w.y;
     return;
@@ -174,7 +197,7 @@ __device__ __forceinline__ void load_row(const void* src, int64_t off, bool acti
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     uint4 w = make_uint4(fill, fill, fill, fill);
-    if (active) w = p[q];
+    if (active) w = ld_global(p + q);
     rw.w[4 * q] = w.x;
     rw.w[4 * q + 1] = w.y;
     rw.w[4 * q + 2] = w.z;
@@ -207,12 +230,8 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
   RowWords<N, DT> yw;
   if constexpr (DT == DT_U8) {
 #pragma unroll
-    for (int d = 0; d < N / 4; ++d) {
-      int y[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) y[b] = round_shift_u8<S>(z[4 * d + b]);
-      yw.w[d] = static_cast<uint32_t>(y[0] | (y[1] << 8) | (y[2] << 16) | (y[3] << 24));
-    }
+    for (int d = 0; d < N / 4; ++d)
+      yw.w[d] = pack_round_u8<S>(z[4 * d], z[4 * d + 1], z[4 * d + 2], z[4 * d + 3]);
   } else {
 #pragma unroll
     for (int d = 0; d < N / 2; ++d) {
@@ -258,12 +277,7 @@ __device__ __forceinline__ unsigned long long store_row(void* dst, int64_t off, 
   return err;
 }
 
-__device__ __forceinline__ int quantise(int b, int32_t mq) {
-  const uint32_t mag = static_cast<uint32_t>(b < 0 ? -b : b);
-  const uint64_t prod = static_cast<uint64_t>(mag) * static_cast<uint32_t>(mq) + (1ull << 23);
-  const int lev = static_cast<int>(prod >> 24);
-  return b < 0 ? -lev : lev;
-}
+__device__ __forceinline__ int quantise(int b, int32_t mq) { return quantise_level(b, quant_mult(mq)); }
 
 // Column j of tile k after the row pass (stored column-major, j < KB).
 template <int N, int BS, int KB = N>
@@ -335,7 +349,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
       const int32_t mq = QUANT && !LEVELS ? sh.mq[w >> 16] : 0;
       int e = p;
       for (int k = 0; k < io.nact; ++k, e += r) {
-        const int val = S[k * C::TS + off];
+        const int val = S[__mul24(k, C::TS) + off];
         st_stream(kept + e, static_cast<uint32_t>(QUANT && !LEVELS ? quantise(val, mq) : val));
       }
     }
@@ -353,7 +367,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
   const int dk = static_cast<int>((static_cast<float>(BS) + 0.5f) * rr), dp = BS - dk * r;
   for (int e = threadIdx.x; e < total; e += BS) {
     const int w = sh.zz[p];
-    const int val = S[k * C::TS + (w & 0xffff)];
+    const int val = S[__mul24(k, C::TS) + (w & 0xffff)];
     const int ci = w >> 16;
     if (io.kept != nullptr) {
       const int b = QUANT && !LEVELS ? quantise(val, sh.mq[ci]) : val;
@@ -416,7 +430,11 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   // inverted: its transform is skipped, which whole waves do at small r
   // (a wave holds 64 / TPW consecutive columns).
   const int j = a_idx;
-  const int keep = j < KB ? sh.cnt[j] : 0;
+  int keep;
+  if constexpr (keep_from_table<N, KB>())
+    keep = j < KB ? kKeepRows8.c[min(io.r, 64)][j] : 0;
+  else
+    keep = j < KB ? sh.cnt[j] : 0;
   int c[N];
   if (keep > 0) {
     read_column<N, BS, KB>(S, j, k, c);
@@ -428,24 +446,35 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
     for (int v = 0; v < N; ++v) c[v] = 0;
   }
   const int cls_u = sh.cls[j];
-  int mq_u[RC.count], dq_u[RC.count];
+  double m_u[RC.count];
+  int dq_u[RC.count];
   if constexpr (QUANT) {
 #pragma unroll
     for (int q = 0; q < RC.count; ++q) {
-      mq_u[q] = sh.mq[q * 4 + cls_u];
+      m_u[q] = quant_mult(sh.mq[q * 4 + cls_u]);
       dq_u[q] = sh.dq[q * 4 + cls_u];
     }
   }
   __syncthreads();  // S is free again
 
-  // zonal mask (a prefix of the column) and quantisation levels; when the
-  // scaled values are not wanted the levels themselves are staged for the
-  // outputs, otherwise the coefficients (the gather quantises them again)
+  // zonal mask (a prefix of the column; nothing to mask when every
+  // coefficient is kept) and quantisation levels; when the scaled values are
+  // not wanted the levels themselves are staged for the outputs, otherwise
+  // the coefficients (the gather quantises them again)
   int lev[N];
+  if (KB == N && io.r >= N * N) {   // uniform: every coefficient kept
 #pragma unroll
-  for (int v = 0; v < N; ++v) {
-    const int b = v < KB && v < keep ? c[v] : 0;
-    lev[v] = QUANT ? quantise(b, mq_u[RC.cls[v]]) : b;
+    for (int v = 0; v < N; ++v) {
+      if constexpr (QUANT) lev[v] = quantise_level(c[v], m_u[RC.cls[v]]);
+      else lev[v] = c[v];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < N; ++v) {
+      const int b = v < KB && v < keep ? c[v] : 0;
+      if constexpr (QUANT) lev[v] = quantise_level(b, m_u[RC.cls[v]]);
+      else lev[v] = b;
+    }
   }
   if (io.kept != nullptr || io.scaled != nullptr) {
     if (QUANT && io.scaled == nullptr) {

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void compress_jam(PassParams p) {
   __shared__ int S[C::WORDS];
   __shared__ Shared<N> sh;
   __shared__ unsigned long long red[kBlock / 64];
-  load_tables<N, kBlock>(sh, p.t, p.r);
+  load_tables<KIND, N, kBlock, KB>(sh, p.t, p.r);
   const int img = blockIdx.z, ty = blockIdx.y, wx = blockIdx.x;
   const int groups_x = (p.g.tiles_x + C::TPW - 1) / C::TPW;
   const int g0 = wx * p.gpw;
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
   __shared__ int S[C::WORDS];
   __shared__ Shared<N> sh;
   const int r = p.r;
-  load_tables<N, kBlock>(sh, p.t, r);
+  load_tables<KIND, N, kBlock>(sh, p.t, r);
   const WgPos w = wg_pos<N>(p.g, blockIdx.x);
   const int a_idx = threadIdx.x / C::TPW;
   const int k = threadIdx.x % C::TPW;

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(jam::kBlock) void serve_jam(const SReq* reqs, const
   const int item = blockIdx.x;
   const int q = find_request(begins, n_req, item);
   const SReq& rq = reqs[q];
-  jam::load_tables<N, jam::kBlock>(sh, rq.t, rq.r);
+  jam::load_tables<KIND, N, jam::kBlock, KB>(sh, rq.t, rq.r);
   const int local = item - begins[q];
   const int ty = local / rq.groups_x;
   const int tx0 = (local - ty * rq.groups_x) * C::TPW;
@@ -212,6 +212,7 @@ struct Slot {
   hipEvent_t done = nullptr;
   std::vector<Member> members;   // submission order
   int64_t id = -1;
+  double launch_ms = 0.0;        // server clock at the flush that launched it
 };
 
 struct Block {
@@ -492,6 +493,7 @@ int do_flush(adct_server* s, int* launched) {
   }
   // the slot's work follows whatever the caller's stream has queued (the inputs)
   const hipStream_t st = sl.stream;
+  sl.launch_ms = s->clock_ms();
   hipError_t e = hipEventRecord(sl.ready, s->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, sl.ready, 0);
   // one upload: request records, first-item offsets and zeroed error energies
@@ -562,6 +564,7 @@ int do_poll(adct_server* s, int wait, adct_completion_t* out, int max_out, int* 
       c.batch = sl.id;
       c.sse = sl.h_sse[mb.table];
       c.done_ms = done;
+      c.launch_ms = sl.launch_ms;
       c.d_kept = reinterpret_cast<const int32_t*>(s->arena + mb.off + mb.kept_off);
       c.d_scaled = mb.scaled_off >= 0
                        ? reinterpret_cast<const float*>(s->arena + mb.off + mb.scaled_off)
@@ -659,7 +662,7 @@ ADCT_API double adct_server_clock_ms(const adct_server_t* s) {
 
 ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* requests,
                                    const double* arrival_ms, int64_t n, double* latency_ms,
-                                   int64_t* batch_of, uint64_t* sse) {
+                                   int64_t* batch_of, uint64_t* sse, double* launch_ms) {
   if (s == nullptr || n < 0 || (n > 0 && (requests == nullptr || arrival_ms == nullptr)))
     return set_error(ADCT_E_ARG, "server: bad trace arguments");
   for (int64_t i = 1; i < n; ++i)
@@ -671,6 +674,7 @@ ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* reque
   if (int st = ensure_device(s)) return st;
   for (int64_t i = 0; i < n; ++i) {
     if (latency_ms) latency_ms[i] = NAN;
+    if (launch_ms) launch_ms[i] = NAN;
     if (batch_of) batch_of[i] = -1;
     if (sse) sse[i] = 0;
   }
@@ -685,6 +689,7 @@ ADCT_API int adct_server_run_trace(adct_server_t* s, const adct_request_t* reque
     for (int k = 0; k < got; ++k) {
       const int64_t i = done[k].tag;
       if (latency_ms) latency_ms[i] = done[k].done_ms - (start + arrival_ms[i]);
+      if (launch_ms) launch_ms[i] = done[k].launch_ms - start;
       if (batch_of) batch_of[i] = done[k].batch;
       if (sse) sse[i] = done[k].sse;
     }

@@ -46,13 +46,13 @@ __device__ __forceinline__ void load_raw(const void* src, int64_t off, int64_t p
     if constexpr (DT == DT_U8) {
       uint2 w = make_uint2(0x80808080u, 0x80808080u);
       if (active)
-        w = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(src) + off + i * pitch);
+        w = ld_global(reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(src) + off + i * pitch));
       raw.w[i][0] = w.x;
       raw.w[i][1] = w.y;
     } else {
       uint4 w = make_uint4(0u, 0u, 0u, 0u);
       if (active)
-        w = *reinterpret_cast<const uint4*>(static_cast<const int16_t*>(src) + off + i * pitch);
+        w = ld_global(reinterpret_cast<const uint4*>(static_cast<const int16_t*>(src) + off + i * pitch));
       raw.w[i][0] = w.x;
       raw.w[i][1] = w.y;
       raw.w[i][2] = w.z;
@@ -180,12 +180,7 @@ __device__ __forceinline__ void inverse2d(int (&a)[kN][kN]) {
   for (int i = 0; i < kN; ++i) inv8<KIND>(a[i]);          // rows:    (K B) K^T
 }
 
-__device__ __forceinline__ int quantise(int b, int32_t mq) {
-  const uint32_t mag = static_cast<uint32_t>(b < 0 ? -b : b);
-  const uint64_t prod = static_cast<uint64_t>(mag) * static_cast<uint32_t>(mq) + (1ull << 23);
-  const int lev = static_cast<int>(prod >> 24);
-  return b < 0 ? -lev : lev;
-}
+__device__ __forceinline__ int quantise(int b, int32_t mq) { return quantise_level(b, quant_mult(mq)); }
 
 // Index of (v, u) in the class tables; the row classes of T8 are known at
 // compile time, so with unrolled v, u this folds to a constant offset.

@@ -261,3 +261,37 @@ def test_64_point_level_fits_int32_for_8bit_input_only(kind):
     assert worst * 128 <= INT32
     # and the whole int16 range would not fit: the library refuses it at N = 64
     assert worst * XMAX > INT32
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_quantiser_float64_evaluation_is_exact(n):
+    """The kernels evaluate level = sign(b) floor(|b| MQ / 2^24 + 1/2) as
+    trunc(copysign(|b| m + 1/2, b)) in float64 with m = MQ / 2^24.  With
+    |b| MQ < 2^47 (bounded above for every transform, N and step) |b| m + 1/2
+    is a multiple of 2^-24 below 2^24, so it is exact in float64 and its
+    truncation is the floor.  Checked here against the integer form on the
+    largest |b| and MQ, on exact ties and on random pairs, with Python's
+    float64 (the product and the sum are exact, as the fused multiply-add
+    is)."""
+    from oracle import pipeline as P
+    rng = np.random.default_rng(n)
+    for kind in (M.KINDS if n > 8 else M.KINDS + M.COMPARISON_KINDS):
+        T = M.transform_matrix(kind, n).astype(np.float64)
+        d = np.diag(T @ T.T)
+        bmax = int(np.abs(T).sum(1).max() ** 2 * XMAX)
+        for q in (1, 3, 16, 255, 4096):
+            g = q * np.sqrt(np.outer(d, d))
+            mqs = np.unique(np.vectorize(lambda x: round_half_away(2 ** 24 / x))(g)).astype(np.int64)
+            assert bmax * int(mqs.max()) < 2 ** 47
+            bs = np.concatenate([[0, 1, -1, bmax, -bmax], rng.integers(-bmax, bmax + 1, 2000)])
+            for mq in mqs:
+                m = float(mq) * 2.0 ** -24
+                got = [int(math.copysign(abs(float(b)) * m + 0.5, float(b))) for b in bs]
+                want = P.quantise(bs, np.full(bs.shape, mq))
+                assert np.array_equal(np.array(got, dtype=np.int64), want), (kind, q, mq)
+    # exact ties: |b| MQ = k 2^24 + 2^23 rounds away from zero
+    for mq in (1 << 23, 3 << 22, (1 << 24) - 1):
+        m = float(mq) * 2.0 ** -24
+        for b in range(-4097, 4098, 7):
+            want = int(P.quantise(np.array([b]), np.array([mq]))[0])
+            assert int(math.copysign(abs(float(b)) * m + 0.5, float(b))) == want, (b, mq)

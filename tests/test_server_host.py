@@ -142,5 +142,5 @@ def test_clock_is_monotonic():
 def test_request_record_layout():
     # the numpy mirrors must match the C structs field for field
     assert adct.REQUEST.itemsize == 80
-    assert adct.COMPLETION.itemsize == 56
+    assert adct.COMPLETION.itemsize == 64
     assert list(adct.REQUEST.names[:5]) == ["d_src", "h_kept", "h_scaled", "h_recon", "pitch"]
