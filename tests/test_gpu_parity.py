@@ -95,6 +95,25 @@ def test_compress_jam_u8(kind, n, r):
 
 @pytest.mark.parametrize("kind", M.KINDS)
 @pytest.mark.parametrize("n", [16, 32])
+@pytest.mark.parametrize("dtype", ["u8", "i16"])
+def test_compress_jam_kept_only(kind, n, dtype):
+    """Kept coefficients without the scaled output, through every kept bound
+    (4 columns for r <= 10, 8 for r <= 36, N above)."""
+    h, w = SHAPES[n]
+    imgs = u8_images(2, h, w, 350) if dtype == "u8" else i16_images(2, h, w, 360)
+    x = to_dev(np.stack(imgs))
+    for r in (1, 2, 3, 5, 6, 9, 10, 11, 15, 21, 28, 35, 36, 37, 100):
+        out = adct.compress(x, kind, n, r, scaled=False)
+        assert out["scaled"] is None
+        want, sse = oracle_batch(imgs, kind, n, r, 0)
+        assert np.array_equal(host(out["kept"]), want["kept"]), r
+        rec = host(out["recon"])
+        assert np.array_equal(rec.reshape(want["recon"].shape), want["recon"]), r
+        assert host(out["sse"]).astype(np.int64).tolist() == sse, r
+
+
+@pytest.mark.parametrize("kind", M.KINDS)
+@pytest.mark.parametrize("n", [16, 32])
 @pytest.mark.parametrize("r", [6, "all"])
 def test_compress_jam_i16(kind, n, r):
     r = n * n if r == "all" else r
