@@ -306,6 +306,9 @@ def main():
     ap.add_argument("--gen-workers", type=int, default=None,
                     help="host workers for input generation and the oracle (default: the "
                          "CPUs available, at most 16; threads under a profiler)")
+    ap.add_argument("--ceiling-footprint", action="store_true",
+                    help="ceiling: also time the best read/write/copy form of the 4 GiB "
+                         "sweep on buffers of 0.25 to 16 GiB")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy kernel first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -662,11 +665,46 @@ def run_ceiling(args):
                     best = {"GBps": round(gbs, 1), "ms": round(ms, 4), "workgroups": blocks,
                             "unroll": unroll}
         results[name] = best
+    footprint = None
+    if args.ceiling_footprint:
+        # the best form of each pattern on smaller and larger buffers (one
+        # 16 GiB pair at most: 32 GiB of the 288 GB)
+        del src, dst
+        torch.cuda.empty_cache()
+        footprint = {}
+        for gib in (0.25, 1, 2, 4, 8, 16):
+            nbytes = int(gib * (1 << 30))
+            src = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+            dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            row = {}
+            for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+                best = results[name]
+
+                def go():
+                    _lib.check(lib.adct_stream_ceiling(pattern, C.c_void_p(dst.data_ptr()),
+                                                       C.c_void_p(src.data_ptr()), nbytes,
+                                                       best["workgroups"], best["unroll"], sp))
+                for _ in range(max(1, args.warmup)):
+                    go()
+                a = torch.cuda.Event(enable_timing=True)
+                z = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(args.steps):
+                    go()
+                z.record(stream)
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(z) / args.steps
+                row[name] = round(moved * nbytes / ms / 1e6, 1)
+            log(f"footprint {gib} GiB per buffer: {row}")
+            footprint[str(gib)] = row
+            del src, dst
+            torch.cuda.empty_cache()
     print(json.dumps({"workload": "HBM streaming ceilings, 4 GiB per buffer, 16-byte "
                                   "non-temporal accesses", "peak_GBps": HBM_PEAK_GBS,
                       "ceilings": results,
                       "fraction_of_peak": {k: round(v["GBps"] / HBM_PEAK_GBS, 4)
-                                           for k, v in results.items()}}), flush=True)
+                                           for k, v in results.items()},
+                      "footprint_GBps": footprint}), flush=True)
 
 
 # ---------------------------------------------------------------- one config
