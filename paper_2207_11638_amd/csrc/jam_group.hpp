@@ -457,42 +457,44 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   }
   __syncthreads();  // S is free again
 
-  // zonal mask (a prefix of the column; nothing to mask when every
-  // coefficient is kept) and quantisation levels; when the scaled values are
-  // not wanted the levels themselves are staged for the outputs, otherwise
-  // the coefficients (the gather quantises them again)
-  int lev[N];
+  // Outputs, then the zonal mask (a prefix of the column; nothing to mask
+  // when every coefficient is kept) and the quantisation levels, in place: a
+  // column holds one array of N values.  With the scaled values wanted the
+  // coefficients are staged before that (the gather quantises the kept
+  // ones itself); otherwise the levels (or the kept coefficients) after it.
+  const bool outs = io.kept != nullptr || io.scaled != nullptr;
+  if (outs && io.scaled != nullptr) {
+    write_column_rows<N, BS, KB, KB>(S, j, k, c);   // [k][v][u], rows v < KB
+    __syncthreads();
+    gather_outputs<N, QUANT, false, BS, KB>(S, sh, io);
+    __syncthreads();
+  }
   if (KB == N && io.r >= N * N) {   // uniform: every coefficient kept
+    if constexpr (QUANT) {
 #pragma unroll
-    for (int v = 0; v < N; ++v) {
-      if constexpr (QUANT) lev[v] = quantise_level(c[v], m_u[RC.cls[v]]);
-      else lev[v] = c[v];
+      for (int v = 0; v < N; ++v) c[v] = quantise_level(c[v], m_u[RC.cls[v]]);
     }
   } else {
 #pragma unroll
     for (int v = 0; v < N; ++v) {
       const int b = v < KB && v < keep ? c[v] : 0;
-      if constexpr (QUANT) lev[v] = quantise_level(b, m_u[RC.cls[v]]);
-      else lev[v] = b;
+      if constexpr (QUANT) c[v] = quantise_level(b, m_u[RC.cls[v]]);
+      else c[v] = b;
     }
   }
-  if (io.kept != nullptr || io.scaled != nullptr) {
-    if (QUANT && io.scaled == nullptr) {
-      write_column_rows<N, BS, KB, KB>(S, j, k, lev);   // [k][v][u], rows v < KB
-      __syncthreads();
-      gather_outputs<N, QUANT, true, BS, KB>(S, sh, io);
-    } else {
-      write_column_rows<N, BS, KB, KB>(S, j, k, c);
-      __syncthreads();
-      gather_outputs<N, QUANT, false, BS, KB>(S, sh, io);
-    }
+  if (outs && io.scaled == nullptr) {
+    write_column_rows<N, BS, KB, KB>(S, j, k, c);
+    __syncthreads();
+    gather_outputs<N, QUANT, QUANT, BS, KB>(S, sh, io);
     __syncthreads();
   }
   if (io.dst == nullptr && !io.sse) return 0ull;
 
   // dequantise
+  if constexpr (QUANT) {
 #pragma unroll
-  for (int v = 0; v < N; ++v) c[v] = QUANT ? __mul24(lev[v], dq_u[RC.cls[v]]) : lev[v];
+    for (int v = 0; v < N; ++v) c[v] = __mul24(c[v], dq_u[RC.cls[v]]);
+  }
 
   // phase 2b: columns, inverse (a column with nothing kept stays zero)
   if (keep > 0) {
