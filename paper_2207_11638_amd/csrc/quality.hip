@@ -12,15 +12,18 @@
 //               once, in float32.
 //   PSNR        10 log10(255^2 H W / SSE) per image, in float32.
 //
-// The moment kernel reuses the row-group code of the 16/32-point kernels: a
-// 256-thread workgroup transforms 256/N horizontally adjacent tiles (row
-// pass, LDS exchange, column pass) and stages all N^2 coefficients of each
-// tile in LDS.  Thread t then owns coefficient positions t, t + 256, ...
-// (N >= 16) or position t mod 64 of every fourth tile (N = 8) and keeps
-// running sums of them in registers while the workgroup walks its share of
-// the image's tile groups; one set of 64-bit atomics per workgroup adds them
-// to the image's record.  Squares are split into their low and high 32-bit
-// halves, each summed in 64 bits, so every sum is exact for any int16 input.
+// For N >= 16 the moment kernel reuses the row-group code of the 16/32-point
+// kernels: a 256-thread workgroup transforms 256/N horizontally adjacent
+// tiles (row pass, LDS exchange, column pass) and stages all N^2
+// coefficients of each tile in LDS.  Thread t then owns coefficient
+// positions t, t + 256, ... and keeps running sums of them in registers
+// while the workgroup walks its share of the image's tile groups; one set of
+// 64-bit atomics per workgroup adds them to the image's record.  For N = 8
+// one thread owns one tile (as in the fused 8-point kernels) and one-wave
+// workgroups exchange the coefficients through LDS, lane p summing position
+// p.  Squares are split into their low and high 32-bit halves, each summed
+// in 64 bits, so every sum is exact for any int16 input (for 8-bit input the
+// bound on |b| lets runs of squares be summed in 32 bits first).
 #include <algorithm>
 #include <type_traits>
 
@@ -141,6 +144,7 @@ constexpr bool small_squares() {
 
 template <int KIND, int N, int DT>
 __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
+  static_assert(N >= 16, "8 x 8 tiles: moments8_kernel");
   using C = Cfg<N>;
   constexpr int NN = N * N;
   constexpr int PPT = NN >= kBlock ? NN / kBlock : 1;      // positions per thread
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
   // U tile groups per step, q0 + u wpi (u < U): their rows are all loaded
   // before the first is transformed, so a workgroup keeps U row loads in
   // flight (the walk covers the image's groups b, b + wpi, ... exactly once)
-  constexpr int U = N == 8 ? 4 : (N == 16 ? 2 : 1);
+  constexpr int U = N == 16 ? 2 : 1;
   for (int64_t q0 = blockIdx.x; q0 < groups; q0 += static_cast<int64_t>(U) * p.wpi) {
     RowWords<N, DT> xs[U];
     int nacts[U];
@@ -322,6 +326,9 @@ __global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
   constexpr int NN = kN * kN;
   constexpr int RS = NN + 1;
   constexpr bool SMALL = small_squares<KIND, 8, DT>();
+  constexpr TransformInfo<8> kInf = make_info<KIND, 8>();
+  constexpr unsigned long long kBmax = 128ull * kInf.l1max * kInf.l1max;   // largest |b|
+  constexpr int SQ_RUN = kBmax * kBmax * 32 < (1ull << 32) ? 32 : 1;
   // 8-bit input where every |b| < 2^15: the exchange holds 16-bit words (half
   // the LDS of a wave, twice the waves per CU)
   using Word = typename std::conditional<SMALL, short, int>::type;
@@ -374,22 +381,33 @@ __global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
       for (int u = 0; u < kN; ++u) lds[lane * RS + v * kN + u] = static_cast<Word>(a[v][u]);
     __syncthreads();
     // lane = coefficient position; tiles of the group one after the other.
-    // The group's sum stays in 32 bits (64 |b| < 2^21); squares go straight
-    // to 64 bits (64 of them can reach 2^32: an all-zero image has |DC| = 2^13).
-    int g1 = 0;
-    for (int t = 0; t < w.nact; ++t) {
-      const int b = static_cast<int>(lds[t * RS + lane]);
-      if constexpr (SMALL) {
-        g1 += b;
-        s2lo += static_cast<uint32_t>(__mul24(b, b));   // |b| < 2^15: b^2 < 2^30
-      } else {
+    // The group's sum stays in 32 bits (64 |b| < 2^21).  Squares are summed
+    // in 32 bits over runs of SQ_RUN tiles (as many as keep the run's sum
+    // below 2^32 at the largest |b|; 32 for every 8-point transform, whose
+    // |b| <= 2^13), then added to the 64-bit total.
+    if constexpr (SMALL) {
+      int g1 = 0;
+      for (int t0 = 0; t0 < w.nact; t0 += SQ_RUN) {
+        const int t1 = min(t0 + SQ_RUN, w.nact);
+        uint32_t g2 = 0;
+#pragma unroll 8
+        for (int t = t0; t < t1; ++t) {
+          const int b = static_cast<int>(lds[t * RS + lane]);
+          g1 += b;
+          g2 += static_cast<uint32_t>(__mul24(b, b));   // |b| < 2^15: b^2 < 2^30
+        }
+        s2lo += g2;
+      }
+      s1 += g1;
+    } else {
+      for (int t = 0; t < w.nact; ++t) {
+        const int b = static_cast<int>(lds[t * RS + lane]);
         s1 += b;
         const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
         s2lo += static_cast<uint32_t>(sq);
         s2hi += sq >> 32;
       }
     }
-    if constexpr (SMALL) s1 += g1;
     tiles += w.nact;
     __syncthreads();   // the next group rewrites the LDS area
   }
