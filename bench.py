@@ -641,7 +641,9 @@ def run_ceiling(args):
     stream = torch.cuda.current_stream()
     sp = C.c_void_p(stream.cuda_stream)
     results = {}
-    for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+    for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2),
+                                 (3, "read_chunked", 1), (4, "write_chunked", 1),
+                                 (5, "copy_chunked", 2)):
         best = None
         for blocks in (2048, 8192, 16384, 32768, 65536):
             for unroll in ((1,) if pattern == 1 else (1, 2, 4, 8)):
@@ -677,7 +679,9 @@ def run_ceiling(args):
             src = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
             dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             row = {}
-            for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+            for pattern, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2),
+                                         (3, "read_chunked", 1), (4, "write_chunked", 1),
+                                         (5, "copy_chunked", 2)):
                 best = results[name]
 
                 def go():

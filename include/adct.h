@@ -315,8 +315,10 @@ ADCT_API int adct_coding_gain_ar1(int transform, int n, int basis, int count,
  * zero-filled input produces; pass a zero-filled d_src), 1 writes `bytes` of
  * zeros to d_dst, 2 copies `bytes` from d_src to d_dst; 16-byte non-temporal
  * accesses, `blocks` workgroups of 256 threads in grid-stride order with
- * `unroll` (1, 2, 4 or 8) independent loads in flight per thread.  bytes a
- * multiple of 16, buffers 16-byte aligned.
+ * `unroll` (1, 2, 4 or 8) independent loads in flight per thread.  Patterns
+ * 3, 4 and 5 are the same read, write and copy with each workgroup walking
+ * one contiguous chunk of the buffer.  bytes a multiple of 16, buffers
+ * 16-byte aligned.
  * ---------------------------------------------------------------------- */
 ADCT_API int adct_stream_ceiling(int pattern, void* d_dst, const void* d_src, int64_t bytes,
                                  int blocks, int unroll, adct_stream_t stream);

@@ -128,6 +128,12 @@ def test_other_entry_points_validate(lib):
     assert lib.adct_get_matrix(1, 12, 0, p) == -1
     assert lib.adct_zigzag(7, p) == -1
     assert lib.adct_quant_tables(1, 8, 0, p, p) == -1
+    # streaming ceilings: patterns 0-5, 16-byte multiples, a source unless writing
+    assert lib.adct_stream_ceiling(6, p, p, 16, 1, 1, None) == -1
+    assert lib.adct_stream_ceiling(2, p, p, 24, 1, 1, None) == -1
+    assert lib.adct_stream_ceiling(5, p, None, 16, 1, 1, None) == -1
+    assert lib.adct_stream_ceiling(3, p, p, 16, 1, 3, None) == -1
+    assert lib.adct_stream_ceiling(4, p, None, 0, 1, 1, None) == 0     # nothing to write
 
 
 def test_quality_entry_points_validate(lib):
