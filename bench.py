@@ -874,9 +874,10 @@ def run_c2(args):
     sse = torch.zeros(len(planes), dtype=torch.uint64, device=dev)
     psnr = torch.zeros(len(planes), dtype=torch.float32, device=dev)
     t0 = time.perf_counter()
-    for i, pl in enumerate(plans.values()):
-        pl.tune(src, dst, kept, None, sse)
-        log(f"tuned plan {i + 1}/{len(plans)} ({time.perf_counter() - t0:.1f} s)")
+    for i, (c, pl) in enumerate(plans.items()):
+        chosen = pl.tune(src, dst, kept, None, sse)
+        log(f"tuned plan {i + 1}/{len(plans)} {c}: shapes {chosen.tolist()} "
+            f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
 
     def step(events=None):

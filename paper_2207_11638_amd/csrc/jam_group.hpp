@@ -12,12 +12,18 @@
 // 256 B (uint8) or 512 B (int16) per image row.  Each 1D N-point butterfly
 // runs on N values in one thread's registers; the row<->column exchange goes
 // through LDS with a padded layout (column stride N+1, tile stride 32/TPW mod
-// 32 words) that keeps the LDS accesses of a half-wave on few banks.
+// 32 words) that keeps the LDS accesses of a half-wave on few banks.  The
+// coefficients that leave in zig-zag order sit in a [v][u] layout of row
+// stride ZS = N+2 (N+1 for N = 8).  Consecutive zig-zag positions step along
+// anti-diagonals, (v, u) -> (v+1, u-1), which moves ZS - 1 words: at ZS = N+1
+// that is N words, a multiple of the 32 banks for N = 32 and 64, and the
+// lanes of one gather read that share an anti-diagonal (up to 26 of 32 at
+// N = 32) queue on one bank; at N+2 they spread over distinct banks.
 //
 // The kept bound KB (every retained coefficient has v, u < KB) also bounds
 // what crosses LDS: KB transformed columns after the row pass, KB coefficient
 // rows after the column pass and KB inverse columns before the last pass.
-// A tile then needs max(KB (N+1), N (KB+1)) words instead of N (N+1).
+// A tile then needs max(KB (N+1), N (KB+1), KB ZS) words instead of N ZS.
 #pragma once
 
 #include "adct_internal.hpp"
@@ -37,12 +43,17 @@ constexpr int tile_stride(int words, int spread) {
 // half-wave on 32 distinct banks.
 constexpr int odd_stride(int words) { return words | 1; }
 
+// Row stride of the [v][u] coefficient layout (see the header comment).
+constexpr int coef_stride(int n) { return n == 8 ? n + 1 : n + 2; }
+
 template <int N, int BS = 256, int KB = N>
 struct Cfg {
   static constexpr int TPW = BS / N;                        // tiles per workgroup
-  static constexpr int CS = N + 1;                          // column / coefficient-row stride
+  static constexpr int CS = N + 1;                          // column stride of the forward exchange
   static constexpr int IS = KB + 1;                         // row stride of the inverse exchange
-  static constexpr int NEED = KB * CS > N * IS ? KB * CS : N * IS;
+  static constexpr int ZS = coef_stride(N);                 // row stride of the coefficients
+  static constexpr int NEED0 = KB * CS > N * IS ? KB * CS : N * IS;
+  static constexpr int NEED = NEED0 > KB * ZS ? NEED0 : KB * ZS;
   static constexpr int TS = TPW == 32 ? odd_stride(NEED)   // LDS tile stride (words)
                                        : tile_stride(NEED, 32 / TPW);
   static constexpr int WORDS = TPW * TS;
@@ -57,7 +68,7 @@ constexpr int kMaxWords = Cfg<32>::WORDS;
 
 // Constant tables of one (transform, N, qstep, r), staged in LDS.
 //   zz[p]  (p < r): zig-zag position p of a tile, as its word offset
-//          v (N+1) + u in the padded [v][u] layout (low 16 bits) and its
+//          v ZS + u in the [v][u] coefficient layout (low 16 bits) and its
 //          class-table entry cls[v] * 4 + cls[u] (high bits);
 //   cnt[u]: rows kept in column u (the zig-zag prefix keeps rows 0..cnt-1).
 template <int N>
@@ -71,7 +82,7 @@ struct Shared {
 };
 
 // Zig-zag words of one (transform, N): entry p holds the word offset
-// v (N+1) + u, in the padded [v][u] layout, of the coefficient at scan
+// v ZS + u, in the [v][u] coefficient layout, of the coefficient at scan
 // position p (low 16 bits) and its class-table entry cls[v] * 4 + cls[u]
 // (high bits).  Built at compile time from the row classes of the forward
 // butterfly, the numbering the host tables use.
@@ -86,7 +97,7 @@ constexpr ZigzagWords<N> make_zigzag_words() {
   ZigzagWords<N> z{};
   for (int v = 0; v < N; ++v)
     for (int u = 0; u < N; ++u)
-      z.w[zz_pos(N, v, u)] = (v * (N + 1) + u) | ((rc.cls[v] * 4 + rc.cls[u]) << 16);
+      z.w[zz_pos(N, v, u)] = (v * coef_stride(N) + u) | ((rc.cls[v] * 4 + rc.cls[u]) << 16);
   return z;
 }
 
@@ -288,12 +299,12 @@ __device__ __forceinline__ void read_column(const int* S, int j, int k, int (&c)
 }
 
 // Rows v < ROWS of column j into the coefficient layout [k][v][u] (row stride
-// N + 1, the layout the zig-zag table addresses).
+// ZS, the layout the zig-zag table addresses).
 template <int N, int BS, int ROWS = N, int KB = N>
 __device__ __forceinline__ void write_column_rows(int* S, int j, int k, const int (&c)[N]) {
   using C = Cfg<N, BS, KB>;
 #pragma unroll
-  for (int v = 0; v < ROWS; ++v) S[k * C::TS + v * C::CS + j] = c[v];
+  for (int v = 0; v < ROWS; ++v) S[k * C::TS + v * C::ZS + j] = c[v];
 }
 
 // Inverse exchange: column j < KB of tile k after the inverse column pass,
@@ -321,10 +332,10 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
 }
 
 // Zig-zag outputs of the group: element e = k r + p of the [nact][r] block is
-// coefficient p (zig-zag order) of tile k, read from the padded [k][v][u]
-// layout in S.  Kept values are the coefficients themselves (zonal) or their
-// quantisation levels; scaled values are the coefficients times
-// 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
+// coefficient p (zig-zag order) of tile k, read from the [k][v][u]
+// coefficient layout in S.  Kept values are the coefficients themselves
+// (zonal) or their quantisation levels; scaled values are the coefficients
+// times 1/sqrt(d_v d_u).  Consecutive threads write consecutive words.
 // LEVELS: S holds the quantisation levels already (no scaled output), so the
 // kept words are copied as they are.
 // With only the kept output and r >= BS, thread t owns zig-zag positions

@@ -106,13 +106,13 @@ __global__ __launch_bounds__(kBlock) void forward_jam(PassParams p) {
   if constexpr (DT == DT_U8)
     if (j == 0) c[0] -= 128 * N * N;
   __syncthreads();
-  write_column_rows<N, kBlock>(S, j, k, c);   // padded [k][v][u]
+  write_column_rows<N, kBlock>(S, j, k, c);   // [k][v][u], row stride ZS
   __syncthreads();
   // natural order within a tile, tiles contiguous in global memory
   uint32_t* dst = reinterpret_cast<uint32_t*>(p.cout + w.tile0 * N * N);
   for (int e = threadIdx.x; e < nact * N * N; e += kBlock) {
     const int kk = e / (N * N), v = (e / N) % N, u = e % N;
-    st_stream(dst + e, static_cast<uint32_t>(S[kk * C::TS + v * C::CS + u]));
+    st_stream(dst + e, static_cast<uint32_t>(S[kk * C::TS + v * C::ZS + u]));
   }
 }
 
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
   const int nact = min(C::TPW, p.g.tiles_x - w.tx0);
   __syncthreads();
   // stage this workgroup's coefficients (contiguous in global memory) into the
-  // padded [k][v][u] layout; entries outside the zonal prefix are not read
+  // [k][v][u], row stride ZS layout; entries outside the zonal prefix are not read
   if constexpr (DECOMP) {
     const int32_t* src = p.cin + w.tile0 * r;
     if (threadIdx.x < nact * r) {
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
     const int32_t* src = p.cin + w.tile0 * N * N;
     for (int e = threadIdx.x; e < nact * N * N; e += kBlock) {
       const int kk = e / (N * N), v = (e / N) % N, u = e % N;
-      S[kk * C::TS + v * C::CS + u] = src[e];
+      S[kk * C::TS + v * C::ZS + u] = src[e];
     }
   }
   __syncthreads();
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
   int c[N];
 #pragma unroll
   for (int v = 0; v < N; ++v) {
-    int b = S[k * C::TS + v * C::CS + j];
+    int b = S[k * C::TS + v * C::ZS + j];
     b = v < keep ? b : 0;
     if constexpr (QUANT) b = __mul24(b, sh.dq[RC.cls[v] * 4 + cls_u]);
     c[v] = b;

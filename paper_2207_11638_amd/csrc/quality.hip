@@ -235,12 +235,12 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
       if constexpr (DT == DT_U8)
         if (a_idx == 0) c[0] -= 128 * N * N;   // level shift folded into the DC coefficient
       __syncthreads();
-      write_column_rows<N, kBlock>(S, a_idx, k, c);   // padded [k][v][u]
+      write_column_rows<N, kBlock>(S, a_idx, k, c);   // [k][v][u], row stride ZS
       __syncthreads();
 #pragma unroll
       for (int pq = 0; pq < PPT; ++pq) {
         const int pos = p0 + pq * kBlock;
-        const int off = (pos / N) * C::CS + pos % N;
+        const int off = (pos / N) * C::ZS + pos % N;
         for (int kk = k0; kk < nact; kk += KSTEP) {
           const int b = S[kk * C::TS + off];
           s1[pq] += b;
