@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("c0", "c1", "c2", "c3", "c4", "plain", "ceiling",
-                                           "sweep"),
+                                           "sweep", "compression"),
                     default="c1",
                     help="c0: latency of one 512^2 image; "
                          "c1: the 1024 x 2048^2 sweep (default; the line also carries the "
@@ -277,7 +277,9 @@ def main():
                          "plain: one fused configuration (--n, --transform, --r, --qstep); "
                          "ceiling: the HBM read/write/copy ceilings of plain 16-byte kernels; "
                          "sweep: the transform assessment of section 4.1 (error energy, "
-                         "deviation from diagonality, coding gain minus the KLT's over rho)")
+                         "deviation from diagonality, coding gain minus the KLT's over rho); "
+                         "compression: the still-image experiment of section 5.1 (mean "
+                         "PSNR and SSIM and their APE against the exact DCT for r = 1..45)")
     ap.add_argument("--engine", choices=("butterfly", "mfma"), default="butterfly",
                     help="c1/plain: N=8 uint8 zonal passes on the butterflies or on the int8 "
                          "matrix cores")
@@ -342,6 +344,8 @@ def main():
         run_ceiling(args)
     elif args.workload == "sweep":
         run_sweep(args)
+    elif args.workload == "compression":
+        run_compression(args)
     else:
         run_c1(args)
 
@@ -567,6 +571,105 @@ def gpu_c1(args, imgs, cpu):
 
 
 # ------------------------------------------------- transform assessment sweep
+def run_compression(args):
+    """Section 5.1's still-image experiment on synthetic stand-ins: 30
+    seeded 512 x 512 uint8 AR(1) images (rho 0.80 .. 0.98, one per image; the
+    paper's 30 standard images are not available) compressed by every 8-point
+    transform of the library and the exact DCT at r = 1..45.  Per (T, r): mean
+    PSNR and mean SSIM over the images and the mean over the images of their
+    absolute percentage errors against the exact DCT's (Figs. 3 and 4).  A
+    sample is checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2207_11638_amd as adct
+    import synth
+
+    n_img = args.images or 30
+    size = 512
+    rhos = [0.80 + 0.18 * i / max(1, n_img - 1) for i in range(n_img)]
+    imgs = [synth.ar1_image(size, size, rho=r_, seed=5100 + i) for i, r_ in enumerate(rhos)]
+    dev = gpu_device()
+    x = torch.from_numpy(np.stack(imgs)).to(dev)
+    recon = torch.empty_like(x)
+    sse = torch.zeros(n_img, dtype=torch.uint64, device=dev)
+    names = {adct.ADCT_T1: "T1", adct.ADCT_T2: "T2", adct.ADCT_SDCT: "SDCT",
+             adct.ADCT_WHT: "WHT", adct.ADCT_HT: "HT", adct.ADCT_DCT: "DCT"}
+    rs = list(range(1, 46))
+    psnr, ssim = {}, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in names:
+        for r in rs:
+            sse.zero_()
+            adct.compress(x, k, 8, r, kept=False, scaled=False, recon=recon, sse=sse)
+            psnr[(k, r)] = adct.psnr(sse, size * size)
+            ssim[(k, r)] = adct.ssim(x, recon)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    curves = {}
+    for k, nm in names.items():
+        c = {"psnr": [], "ssim": [], "psnr_ape": [], "ssim_ape": []}
+        for r in rs:
+            c["psnr"].append(round(float(psnr[(k, r)].mean()), 4))
+            c["ssim"].append(round(float(ssim[(k, r)].mean()), 5))
+            if k != adct.ADCT_DCT:
+                c["psnr_ape"].append(round(float(
+                    adct.ape(psnr[(k, r)], psnr[(adct.ADCT_DCT, r)]).mean()), 4))
+                c["ssim_ape"].append(round(float(
+                    adct.ape(ssim[(k, r)], ssim[(adct.ADCT_DCT, r)]).mean()), 4))
+        curves[nm] = c
+        log(f"{nm}: mean PSNR r=1 {c['psnr'][0]:.2f}, r=10 {c['psnr'][9]:.2f}, r=45 "
+            f"{c['psnr'][44]:.2f} dB; mean SSIM r=10 {c['ssim'][9]:.4f}")
+    # the orderings section 5.1 reports for the standard images; at r = 1 only
+    # the DC coefficient is kept, the same for every transform
+    p = {nm: np.array(curves[nm]["psnr"]) for nm in curves}
+    orderings = {
+        "r = 1: every transform equals the DCT": bool(all(p[nm][0] == p["DCT"][0] for nm in p)),
+        "T2 PSNR above SDCT, 2 <= r <= 45": bool(np.all(p["T2"][1:] > p["SDCT"][1:])),
+        "T2 PSNR above WHT, 2 <= r <= 15": bool(np.all(p["T2"][1:15] > p["WHT"][1:15])),
+        "T2 PSNR above T1, 2 <= r <= 45": bool(np.all(p["T2"][1:] > p["T1"][1:])),
+        "HT PSNR below WHT, 2 <= r <= 45": bool(np.all(p["HT"][1:] < p["WHT"][1:])),
+    }
+    for kk, v in orderings.items():
+        log(f"{kk}: {v}")
+    check = None
+    if not args.no_check:
+        from oracle import metrics as Q
+        from oracle import pipeline as P
+        bad = 0
+        recon_h = {}
+        for k, r in ((adct.ADCT_T2, 5), (adct.ADCT_T1, 20), (adct.ADCT_WHT, 10),
+                     (adct.ADCT_SDCT, 45), (adct.ADCT_DCT, 10)):
+            sse.zero_()
+            adct.compress(x, k, 8, r, kept=False, scaled=False, recon=recon, sse=sse)
+            recon_h[(k, r)] = recon.cpu().numpy()
+            for i in (0, n_img - 1):
+                want = P.compress_dct(imgs[i], r) if k == adct.ADCT_DCT else \
+                    P.compress(imgs[i], k, 8, r)
+                # the float32 DCT may round a pixel whose float64 value lies
+                # within 1e-2 of a tie the other way: compare it within 1e-4
+                tol = 1e-4 if k == adct.ADCT_DCT else 1e-5
+                got_p = float(psnr[(k, r)][i])
+                bad += int(abs(got_p - want["psnr"]) > tol * abs(want["psnr"]))
+                want_s = Q.mean_ssim(imgs[i], want["recon"])
+                got_s = float(ssim[(k, r)][i])
+                bad += int(abs(got_s - want_s) > tol * max(abs(want_s), 1.0))
+                if k != adct.ADCT_DCT:
+                    bad += int(not np.array_equal(recon_h[(k, r)][i], want["recon"]))
+        check = "ok" if bad == 0 else f"{bad} mismatches"
+        log(f"sampled parity vs oracle (5 (T, r) points, images 0 and {n_img - 1}: "
+            f"reconstruction, PSNR, SSIM): {check}")
+    print(json.dumps({"workload": "still-image compression of section 5.1: "
+                                  f"{n_img} AR(1) 512x512 uint8 stand-ins, r = 1..45",
+                      "images": n_img, "rho": [round(rhos[0], 3), round(rhos[-1], 3)],
+                      "gpu_seconds": round(gpu_s, 3),
+                      "passes": len(names) * len(rs),
+                      "ape": "mean over images of 100 |m - m_DCT| / m_DCT",
+                      "curves": curves, "orderings": orderings,
+                      "parity_sample": check}), flush=True)
+
+
 def run_sweep(args):
     """Section 4.1's assessment of every transform the library offers: the
     total error energy and the deviation from diagonality (host, float64) and
