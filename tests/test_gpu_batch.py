@@ -140,6 +140,29 @@ def test_tune_picks_a_valid_shape_and_keeps_results():
         assert np.array_equal(a, b)
 
 
+def test_tune_cache_is_reused_by_a_second_plan(tmp_path, monkeypatch):
+    """With ADCT_TUNE_CACHE set, a second plan over the same TUs finds every
+    choice of the first plan's tuning in the cache (nothing is appended) and
+    makes the same choices."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("ADCT_TUNE_CACHE", str(cache))
+    imgs, descs, tus, arena = make_set("u8", 8100)
+    src = torch.from_numpy(arena).to(DEV)
+    dst = torch.zeros_like(src)
+    plan = adct.BatchPlan(descs, tus, torch.uint8)
+    kept = torch.zeros(plan.kept_words, dtype=torch.int32, device=DEV)
+    chosen = plan.tune(src, dst, kept)
+    lines = cache.read_text().splitlines()
+    assert len(lines) >= len(chosen)
+    again = adct.BatchPlan(descs, tus, torch.uint8)
+    chosen2 = again.tune(src, dst, kept)
+    assert cache.read_text().splitlines() == lines
+    assert chosen2.tolist() == chosen.tolist()
+    assert again.info() == plan.info()
+    for a, b in zip(run_plan(plan, arena, "batched"), run_plan(again, arena, "batched")):
+        assert np.array_equal(a, b)
+
+
 def test_boundary_split_of_residual_frame():
     # 4:2:0 residual planes whose heights are not multiples of 32: CTUs of 32
     # with forced splits on the border only (the implicit split)
