@@ -66,10 +66,16 @@ struct Cfg {
 constexpr int kBlock = 256;
 constexpr int kMaxWords = Cfg<32>::WORDS;
 
+// The zig-zag table is staged in LDS for N <= 32.  At N = 64 it would take
+// 16 KB of the workgroup's 84 KB and hold the full-bound launch to one
+// workgroup per compute unit; there it is read from constant memory.
+template <int N>
+constexpr bool zz_in_lds() { return N <= 32; }
+
 // Constant tables of one (transform, N, qstep, r), staged in LDS.
 //   zz[p]  (p < r): zig-zag position p of a tile, as its word offset
 //          v ZS + u in the [v][u] coefficient layout (low 16 bits) and its
-//          class-table entry cls[v] * 4 + cls[u] (high bits);
+//          class-table entry cls[v] * 4 + cls[u] (high bits) (N <= 32);
 //   cnt[u]: rows kept in column u (the zig-zag prefix keeps rows 0..cnt-1).
 template <int N>
 struct Shared {
@@ -78,7 +84,7 @@ struct Shared {
   float s2[16];
   int32_t cls[N];
   int32_t cnt[N];
-  int32_t zz[N * N];
+  int32_t zz[zz_in_lds<N>() ? N * N : 1];
 };
 
 // Zig-zag words of one (transform, N): entry p holds the word offset
@@ -103,6 +109,14 @@ constexpr ZigzagWords<N> make_zigzag_words() {
 
 template <int KIND, int N>
 static __constant__ ZigzagWords<N> kZigzagWords = make_zigzag_words<KIND, N>();
+
+// Zig-zag word p of a group's tables: from LDS, or from constant memory at
+// N = 64.
+template <int KIND, int N>
+__device__ __forceinline__ int zz_word(const Shared<N>& sh, int p) {
+  if constexpr (zz_in_lds<N>()) return sh.zz[p];
+  else return kZigzagWords<KIND, N>.w[p];
+}
 
 // Kept rows of column u < 8 when the first r <= 64 zig-zag positions of an
 // 8 x 8 block are retained (the zig-zag prefix keeps rows 0 .. c[r][u] - 1).
@@ -158,10 +172,12 @@ __device__ __forceinline__ void load_tables(Shared<N>& sh, const Tables& t, int 
       sh.cnt[i] = cnt;
     }
   }
+  if constexpr (zz_in_lds<N>()) {
 #pragma unroll
-  for (int q = 0; q < (N * N + BS - 1) / BS; ++q) {
-    const int p = i + q * BS;
-    if (p < r) sh.zz[p] = kZigzagWords<KIND, N>.w[p];
+    for (int q = 0; q < (N * N + BS - 1) / BS; ++q) {
+      const int p = i + q * BS;
+      if (p < r) sh.zz[p] = kZigzagWords<KIND, N>.w[p];
+    }
   }
 }
 
@@ -344,7 +360,7 @@ __device__ __forceinline__ void copy_out(uint32_t* dst, const int* src, int coun
 // +7 % on quantised int16 frames).  Otherwise consecutive threads take
 // consecutive (tile, position) elements (with the scaled output as a second
 // stream, the position-major order measured 5-13 % slower).
-template <int N, bool QUANT, bool LEVELS, int BS, int KB = N>
+template <int KIND, int N, bool QUANT, bool LEVELS, int BS, int KB = N>
 __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh,
                                                const GroupIO& io) {
   using C = Cfg<N, BS, KB>;
@@ -355,7 +371,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
     if (io.kept == nullptr) return;
     uint32_t* kept = reinterpret_cast<uint32_t*>(io.kept);
     for (int p = threadIdx.x; p < r; p += BS) {
-      const int w = sh.zz[p];
+      const int w = zz_word<KIND, N>(sh, p);
       const int off = w & 0xffff;
       const int32_t mq = QUANT && !LEVELS ? sh.mq[w >> 16] : 0;
       int e = p;
@@ -377,7 +393,7 @@ __device__ __forceinline__ void gather_outputs(const int* S, const Shared<N>& sh
   int p = threadIdx.x - k * r;
   const int dk = static_cast<int>((static_cast<float>(BS) + 0.5f) * rr), dp = BS - dk * r;
   for (int e = threadIdx.x; e < total; e += BS) {
-    const int w = sh.zz[p];
+    const int w = zz_word<KIND, N>(sh, p);
     const int val = S[__mul24(k, C::TS) + (w & 0xffff)];
     const int ci = w >> 16;
     if (io.kept != nullptr) {
@@ -477,7 +493,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   if (outs && io.scaled != nullptr) {
     write_column_rows<N, BS, KB, KB>(S, j, k, c);   // [k][v][u], rows v < KB
     __syncthreads();
-    gather_outputs<N, QUANT, false, BS, KB>(S, sh, io);
+    gather_outputs<KIND, N, QUANT, false, BS, KB>(S, sh, io);
     __syncthreads();
   }
   if (KB == N && io.r >= N * N) {   // uniform: every coefficient kept
@@ -496,7 +512,7 @@ __device__ __forceinline__ unsigned long long compress_group(int* S, const Share
   if (outs && io.scaled == nullptr) {
     write_column_rows<N, BS, KB, KB>(S, j, k, c);
     __syncthreads();
-    gather_outputs<N, QUANT, QUANT, BS, KB>(S, sh, io);
+    gather_outputs<KIND, N, QUANT, QUANT, BS, KB>(S, sh, io);
     __syncthreads();
   }
   if (io.dst == nullptr && !io.sse) return 0ull;

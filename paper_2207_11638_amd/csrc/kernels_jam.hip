@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void inverse_jam(PassParams p) {
       int q = threadIdx.x - kk * r;
       const int dk = kBlock / r, dq = kBlock - dk * r;
       for (int e = threadIdx.x; e < nact * r; e += kBlock) {
-        S[kk * C::TS + (sh.zz[q] & 0xffff)] = src[e];
+        S[kk * C::TS + (zz_word<KIND, N>(sh, q) & 0xffff)] = src[e];
         q += dq;
         kk += dk;
         if (q >= r) {
