@@ -18,7 +18,8 @@
 // anti-diagonals, (v, u) -> (v+1, u-1), which moves ZS - 1 words: at ZS = N+1
 // that is N words, a multiple of the 32 banks for N = 32 and 64, and the
 // lanes of one gather read that share an anti-diagonal (up to 26 of 32 at
-// N = 32) queue on one bank; at N+2 they spread over distinct banks.
+// N = 32) queue on one bank; at N+2 a step moves N+1 words and at most 4 of
+// 32 lanes meet on a bank.
 //
 // The kept bound KB (every retained coefficient has v, u < KB) also bounds
 // what crosses LDS: KB transformed columns after the row pass, KB coefficient
