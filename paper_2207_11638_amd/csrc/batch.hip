@@ -154,7 +154,11 @@ __device__ __forceinline__ void item_jam(const Outs& o, const BItem& it, const T
   io.kept = o.kept != nullptr ? o.kept + it.kept_base : nullptr;
   io.scaled = o.scaled != nullptr ? o.scaled + it.kept_base : nullptr;
   io.sse = o.sse != nullptr;
-  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, false, KB>(S, sh, io);
+  // non-temporal reconstruction stores for the quantised buckets (whole
+  // frames tiled by one TU size: measured +0.6 % on the residual frames);
+  // plain stores for the zonal ones, whose TU rows share lines with TUs of
+  // other sizes
+  const unsigned long long e = jam::compress_group<KIND, N, DT, QUANT, BS, QUANT, KB>(S, sh, io);
   if (o.sse != nullptr) block_add_sse<BS>(o.sse + it.image, e, red);
 }
 
