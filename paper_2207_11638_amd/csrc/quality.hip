@@ -428,6 +428,185 @@ __global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
   }
 }
 
+// 8 x 8 tiles of 8-bit images on the int8 matrix cores.  With vec(A) the 64
+// pixels of a tile in row-major order, vec(B) = (T (x) T) vec(A - 128); the
+// entries of T lie in {0, +-1, +-2}, so T (x) T and A - 128 (a byte XOR with
+// 0x80) are int8 operands and the int32 products are exact.  One
+// v_mfma_i32_16x16x64_i8 multiplies 16 rows of T (x) T (lane l: row l % 16,
+// pixels 16 (l / 16) .. + 15) by the pixels of 16 tiles (lane l: rows
+// 2 (l / 16), 2 (l / 16) + 1 of tile l % 16), and lane l receives coefficient
+// 16 blk + 4 (l / 16) + t of tile l % 16 in accumulator t of block blk.
+// A wave walks the 64-tile groups q = b, b + wpi, ... of its image (four
+// 16-tile steps, 512 B per pixel row, as the butterfly kernel).  Each lane
+// adds its 16 coefficients and their squares to 32-bit run sums; every RUN
+// groups the wave folds the run sums through LDS into 64-bit totals, lane p
+// owning coefficient position p.  The transform costs the vector units
+// nothing, which leaves about 3 VALU instructions per pixel (run sums,
+// pixel sums, operand bytes) against about 11 in moments8_kernel.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack_i8x4(int a, int b, int c, int d) {
+  return (static_cast<uint32_t>(a) & 0xffu) | ((static_cast<uint32_t>(b) & 0xffu) << 8) |
+         ((static_cast<uint32_t>(c) & 0xffu) << 16) | (static_cast<uint32_t>(d) << 24);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(t8::kWave) void moments8_mfma(MomParams p) {
+  using namespace t8;
+  constexpr int NN = kN * kN;
+  constexpr TransformInfo<8> kInf = make_info<KIND, 8>();
+  constexpr unsigned long long kBmax = 128ull * kInf.l1max * kInf.l1max;   // largest |b|
+  static_assert(kBmax < (1u << 15), "squares of 24-bit products");
+  // groups per run: a lane adds 4 squares per group, and a run's sum of
+  // squares must stay below 2^32
+  constexpr int RUN = 4ull * 8 * kBmax * kBmax < (1ull << 32)   ? 8
+                      : 4ull * 4 * kBmax * kBmax < (1ull << 32) ? 4
+                      : 4ull * 2 * kBmax * kBmax < (1ull << 32) ? 2 : 1;
+  constexpr int FS = 17;   // LDS stride of a lane's 16 run sums
+  __shared__ int fold[2][kWave * FS];
+  const TransformInfo<8>& I = info<KIND, 8>();
+  const int lane = threadIdx.x;
+  const int q = lane >> 4, col = lane & 15;
+
+  // rows 16 blk .. 16 blk + 15 of T (x) T as the A operand of block blk
+  v4i_t fa[4];
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int v = 2 * blk + (col >> 3), u = col & 7;
+    uint32_t w4[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      int f[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int b = 4 * w + e;
+        f[e] = I.t[v][2 * q + (b >> 3)] * I.t[u][b & 7];
+      }
+      w4[w] = pack_i8x4(f[0], f[1], f[2], f[3]);
+    }
+    fa[blk] = v4i_t{static_cast<int>(w4[0]), static_cast<int>(w4[1]), static_cast<int>(w4[2]),
+                    static_cast<int>(w4[3])};
+  }
+
+  const int img = blockIdx.y;
+  const int groups_x = (p.g.tiles_x + 63) / 64;
+  const int64_t groups = static_cast<int64_t>(groups_x) * p.g.tiles_y;
+  const uint8_t* src = static_cast<const uint8_t*>(p.src) + static_cast<int64_t>(img) * p.g.image_stride;
+  const v4i_t zero = {0, 0, 0, 0};
+  // run sums: coefficients accumulated by the matrix cores themselves (the
+  // accumulator operand), squares by the vector units
+  v4i_t s1r[4] = {zero, zero, zero, zero};
+  uint32_t s2r[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s2r[k] = 0;
+  long long t1 = 0, a1 = 0;             // t1, t2: totals of coefficient position `lane`
+  unsigned long long t2 = 0, a2 = 0;
+  long long tiles = 0;
+
+  // the lanes holding position `lane`: 16 (lane >> 2 & 3) + c, sum slot k
+  const int pk = 4 * (lane >> 4) + (lane & 3);
+  const int ph = 16 * ((lane >> 2) & 3);
+  auto fold_run = [&]() {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      fold[0][lane * FS + k] = s1r[k >> 2][k & 3];
+      fold[1][lane * FS + k] = static_cast<int>(s2r[k]);
+      s2r[k] = 0;
+    }
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) s1r[blk] = zero;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      t1 += fold[0][(ph + c) * FS + pk];
+      t2 += static_cast<uint32_t>(fold[1][(ph + c) * FS + pk]);
+    }
+    __syncthreads();
+  };
+
+  // the wave's 16-tile steps, four per group; the rows of step i + 1 are
+  // loaded while step i is computed.  A cursor (tile row, group column,
+  // step) walks the groups blockIdx.x, + wpi, ... without divisions.
+  const int64_t my_groups = blockIdx.x < groups ? (groups - 1 - blockIdx.x) / p.wpi + 1 : 0;
+  const int64_t nsteps = 4 * my_groups;
+  const int dty = p.wpi / groups_x, dgx = p.wpi - dty * groups_x;
+  int cy = static_cast<int>(blockIdx.x) / groups_x;
+  int cx = static_cast<int>(blockIdx.x) - cy * groups_x;
+  int cj = 0;
+  auto load_step = [&](uint2& a, uint2& b) {   // rows 2q, 2q + 1 of the cursor's tile
+    const int tile = 64 * cx + 16 * cj + col;
+    a = make_uint2(0x80808080u, 0x80808080u);
+    b = a;
+    if (tile < p.g.tiles_x) {
+      const uint8_t* x = src + static_cast<int64_t>(8 * cy + 2 * q) * p.g.pitch +
+                         static_cast<int64_t>(tile) * 8;
+      a = ld_global(reinterpret_cast<const uint2*>(x));
+      b = ld_global(reinterpret_cast<const uint2*>(x + p.g.pitch));
+    }
+  };
+  uint2 n0 = make_uint2(0x80808080u, 0x80808080u), n1 = n0;
+  if (nsteps > 0) load_step(n0, n1);
+  int run = 0;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const uint2 r0 = n0, r1 = n1;
+    const int tx0 = 64 * cx;
+    const bool active = tx0 + 16 * cj + col < p.g.tiles_x;
+    const bool last = cj == 3;
+    if (++cj == 4) {   // advance the cursor to step i + 1
+      cj = 0;
+      cx += dgx;
+      cy += dty;
+      if (cx >= groups_x) {
+        cx -= groups_x;
+        ++cy;
+      }
+    }
+    if (i + 1 < nsteps) load_step(n0, n1);
+    if (active) {   // pixel sums of the two rows, level-shifted
+      uint32_t sx = 0, sxx = 0;
+      const uint32_t ws[4] = {r0.x, r0.y, r1.x, r1.y};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sx = __builtin_amdgcn_udot4(ws[k], 0x01010101u, sx, false);
+        sxx = __builtin_amdgcn_udot4(ws[k], ws[k], sxx, false);
+      }
+      a1 += static_cast<long long>(sx) - 128 * 16;
+      a2 += static_cast<unsigned long long>(sxx) + 16384ull * 16 - 256ull * sx;
+    }
+    const v4i_t px = {static_cast<int>(r0.x ^ 0x80808080u), static_cast<int>(r0.y ^ 0x80808080u),
+                      static_cast<int>(r1.x ^ 0x80808080u), static_cast<int>(r1.y ^ 0x80808080u)};
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const v4i_t d = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[blk], px, zero, 0, 0, 0);
+      s1r[blk] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[blk], px, s1r[blk], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s2r[4 * blk + t] += static_cast<uint32_t>(__mul24(d[t], d[t]));
+    }
+    if (last) {   // end of a group (uniform: every lane walks the same steps)
+      tiles += min(64, p.g.tiles_x - tx0);
+      if (++run == RUN) {
+        fold_run();
+        run = 0;
+      }
+    }
+  }
+  if (run > 0) fold_run();
+  unsigned long long* rec = p.mom + static_cast<int64_t>(img) * (3 * NN + 4);
+  if (t1 != 0) atomicAdd(rec + lane, static_cast<unsigned long long>(t1));
+  if (t2 != 0) atomicAdd(rec + NN + lane, t2);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a1 += __shfl_xor(a1, off, 64);
+    a2 += __shfl_xor(a2, off, 64);
+  }
+  if (lane == 0 && tiles > 0) {
+    atomicAdd(rec + 3 * NN, static_cast<unsigned long long>(tiles));
+    atomicAdd(rec + 3 * NN + 1, static_cast<unsigned long long>(tiles) * NN);
+    if (a1 != 0) atomicAdd(rec + 3 * NN + 2, static_cast<unsigned long long>(a1));
+    if (a2 != 0) atomicAdd(rec + 3 * NN + 3, a2);
+  }
+}
+
 // ----------------------------------------------------- measured coding gain
 // count * s2 - s1^2 = count^2 times the population variance, exactly (128-bit)
 __device__ __forceinline__ float scaled_variance(unsigned long long count, unsigned long long s2lo,
@@ -590,7 +769,7 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
     const dim3 grid8(p.wpi, g.batch);
     auto go = [&](auto kind_tag) {
       constexpr int K = decltype(kind_tag)::value;
-      if (dtype == DT_U8) moments8_kernel<K, DT_U8><<<grid8, t8::kWave, 0, s>>>(p);
+      if (dtype == DT_U8) moments8_mfma<K><<<grid8, t8::kWave, 0, s>>>(p);
       else moments8_kernel<K, DT_I16><<<grid8, t8::kWave, 0, s>>>(p);
     };
     switch (kind) {
