@@ -524,9 +524,9 @@ __global__ __launch_bounds__(t8::kWave) void moments8_mfma(MomParams p) {
     __syncthreads();
   };
 
-  // the wave's 16-tile steps, four per group; the rows of step i + 1 are
-  // loaded while step i is computed.  A cursor (tile row, group column,
-  // step) walks the groups blockIdx.x, + wpi, ... without divisions.
+  // the wave's 16-tile steps, four per group, with the rows of the next two
+  // steps in flight while a step is computed.  A cursor (tile row, group
+  // column, step) walks the groups blockIdx.x, + wpi, ... without divisions.
   const int64_t my_groups = blockIdx.x < groups ? (groups - 1 - blockIdx.x) / p.wpi + 1 : 0;
   const int64_t nsteps = 4 * my_groups;
   const int dty = p.wpi / groups_x, dgx = p.wpi - dty * groups_x;
@@ -544,15 +544,12 @@ __global__ __launch_bounds__(t8::kWave) void moments8_mfma(MomParams p) {
       b = ld_global(reinterpret_cast<const uint2*>(x + p.g.pitch));
     }
   };
-  uint2 n0 = make_uint2(0x80808080u, 0x80808080u), n1 = n0;
-  if (nsteps > 0) load_step(n0, n1);
-  int run = 0;
-  for (int64_t i = 0; i < nsteps; ++i) {
-    const uint2 r0 = n0, r1 = n1;
-    const int tx0 = 64 * cx;
-    const bool active = tx0 + 16 * cj + col < p.g.tiles_x;
-    const bool last = cj == 3;
-    if (++cj == 4) {   // advance the cursor to step i + 1
+  // two steps in flight: (n0, n1) holds step i + 1 and (m0, m1) step i + 2
+  // when step i is computed; the cursor stands at the step to load next, and
+  // (ux, uj) at the step computed
+  int ux = cx, uj = 0;
+  auto advance = [&]() {
+    if (++cj == 4) {
       cj = 0;
       cx += dgx;
       cy += dty;
@@ -561,7 +558,27 @@ __global__ __launch_bounds__(t8::kWave) void moments8_mfma(MomParams p) {
         ++cy;
       }
     }
-    if (i + 1 < nsteps) load_step(n0, n1);
+  };
+  uint2 n0 = make_uint2(0x80808080u, 0x80808080u), n1 = n0, m0 = n0, m1 = n0;
+  if (nsteps > 0) load_step(n0, n1);
+  advance();
+  if (nsteps > 1) load_step(m0, m1);
+  advance();
+  int run = 0;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const uint2 r0 = n0, r1 = n1;
+    n0 = m0;
+    n1 = m1;
+    const int tx0 = 64 * ux;
+    const bool active = tx0 + 16 * uj + col < p.g.tiles_x;
+    const bool last = uj == 3;
+    if (++uj == 4) {
+      uj = 0;
+      ux += dgx;
+      if (ux >= groups_x) ux -= groups_x;
+    }
+    if (i + 2 < nsteps) load_step(m0, m1);
+    advance();
     if (active) {   // pixel sums of the two rows, level-shifted
       uint32_t sx = 0, sxx = 0;
       const uint32_t ws[4] = {r0.x, r0.y, r1.x, r1.y};
