@@ -314,25 +314,20 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(MomParams p) {
   }
 }
 
-// 8 x 8 tiles: one thread per tile, one wave per workgroup (as the fused
-// 8-point kernels).  A wave walks the 64-tile groups q = b, b + wpi, ... of
-// its image; for each it transforms its tiles in registers, writes the 64
-// coefficients of each tile to LDS, and lane p then adds position p of all
-// the group's tiles to its running sums (32-bit within a group where the
-// bound allows, 64-bit across groups).  One set of atomics per wave at the end.
-template <int KIND, int DT>
+// 8 x 8 tiles of int16 images (8-bit input takes moments8_mfma): one thread
+// per tile, one wave per workgroup (as the fused 8-point kernels).  A wave
+// walks the 64-tile groups q = b, b + wpi, ... of its image; for each it
+// transforms its tiles in registers, writes the 64 coefficients of each tile
+// to LDS, and lane p then adds position p of all the group's tiles to its
+// running sums, squares split into 32-bit halves summed in 64 bits.  One set
+// of atomics per wave at the end.
+template <int KIND>
 __global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
   using namespace t8;
+  constexpr int DT = DT_I16;
   constexpr int NN = kN * kN;
   constexpr int RS = NN + 1;
-  constexpr bool SMALL = small_squares<KIND, 8, DT>();
-  constexpr TransformInfo<8> kInf = make_info<KIND, 8>();
-  constexpr unsigned long long kBmax = 128ull * kInf.l1max * kInf.l1max;   // largest |b|
-  constexpr int SQ_RUN = kBmax * kBmax * 32 < (1ull << 32) ? 32 : 1;
-  // 8-bit input where every |b| < 2^15: the exchange holds 16-bit words (half
-  // the LDS of a wave, twice the waves per CU)
-  using Word = typename std::conditional<SMALL, short, int>::type;
-  __shared__ Word lds[kWave * RS];
+  __shared__ int lds[kWave * RS];
   const int img = blockIdx.y;
   const int lane = threadIdx.x;
   const int groups_x = (p.g.tiles_x + kWave - 1) / kWave;
@@ -346,67 +341,30 @@ __global__ __launch_bounds__(t8::kWave) void moments8_kernel(MomParams p) {
     const WaveTiles w = wave_tiles_at(p.g, gx, ty, img);
     Raw<DT> raw;
     load_raw<DT>(p.src, w.pix, p.g.pitch, w.active, raw);
-    if (w.active) {   // pixel sums of the tile, level-shifted for 8-bit input
-      if constexpr (DT == DT_U8) {
-        uint32_t sx = 0, sxx = 0;
-#pragma unroll
-        for (int i = 0; i < kN; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            sx = __builtin_amdgcn_udot4(raw.w[i][j], 0x01010101u, sx, false);
-            sxx = __builtin_amdgcn_udot4(raw.w[i][j], raw.w[i][j], sxx, false);
-          }
-        a1 += static_cast<long long>(sx) - 128 * NN;
-        a2 += static_cast<unsigned long long>(sxx) + 16384ull * NN - 256ull * sx;
-      }
-    }
     int a[kN][kN];
     unpack<DT>(raw, a);
-    if constexpr (DT != DT_U8) {
-      if (w.active) {
+    if (w.active) {   // pixel sums of the tile
 #pragma unroll
-        for (int i = 0; i < kN; ++i)
+      for (int i = 0; i < kN; ++i)
 #pragma unroll
-          for (int j = 0; j < kN; ++j) {
-            a1 += a[i][j];
-            a2 += static_cast<unsigned long long>(static_cast<long long>(a[i][j]) * a[i][j]);
-          }
-      }
+        for (int j = 0; j < kN; ++j) {
+          a1 += a[i][j];
+          a2 += static_cast<unsigned long long>(static_cast<long long>(a[i][j]) * a[i][j]);
+        }
     }
     forward2d<KIND>(a);
-    if constexpr (DT == DT_U8) a[0][0] -= 128 * NN;
 #pragma unroll
     for (int v = 0; v < kN; ++v)
 #pragma unroll
-      for (int u = 0; u < kN; ++u) lds[lane * RS + v * kN + u] = static_cast<Word>(a[v][u]);
+      for (int u = 0; u < kN; ++u) lds[lane * RS + v * kN + u] = a[v][u];
     __syncthreads();
-    // lane = coefficient position; tiles of the group one after the other.
-    // The group's sum stays in 32 bits (64 |b| < 2^21).  Squares are summed
-    // in 32 bits over runs of SQ_RUN tiles (as many as keep the run's sum
-    // below 2^32 at the largest |b|; 32 for every 8-point transform, whose
-    // |b| <= 2^13), then added to the 64-bit total.
-    if constexpr (SMALL) {
-      int g1 = 0;
-      for (int t0 = 0; t0 < w.nact; t0 += SQ_RUN) {
-        const int t1 = min(t0 + SQ_RUN, w.nact);
-        uint32_t g2 = 0;
-#pragma unroll 8
-        for (int t = t0; t < t1; ++t) {
-          const int b = static_cast<int>(lds[t * RS + lane]);
-          g1 += b;
-          g2 += static_cast<uint32_t>(__mul24(b, b));   // |b| < 2^15: b^2 < 2^30
-        }
-        s2lo += g2;
-      }
-      s1 += g1;
-    } else {
-      for (int t = 0; t < w.nact; ++t) {
-        const int b = static_cast<int>(lds[t * RS + lane]);
-        s1 += b;
-        const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
-        s2lo += static_cast<uint32_t>(sq);
-        s2hi += sq >> 32;
-      }
+    // lane = coefficient position; tiles of the group one after the other
+    for (int t = 0; t < w.nact; ++t) {
+      const int b = lds[t * RS + lane];
+      s1 += b;
+      const unsigned long long sq = static_cast<unsigned long long>(static_cast<long long>(b) * b);
+      s2lo += static_cast<uint32_t>(sq);
+      s2hi += sq >> 32;
     }
     tiles += w.nact;
     __syncthreads();   // the next group rewrites the LDS area
@@ -778,7 +736,8 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
   if (n == 8) {
     // one-wave workgroups, about 32768 in all (several times what the chip
     // holds at once, so the last ones to start leave little tail), each
-    // walking 64-tile groups of its image
+    // walking 64-tile groups of its image: 8-bit input on the matrix cores,
+    // int16 on the butterflies
     const int64_t groups8 = static_cast<int64_t>((g.tiles_x + 63) / 64) * g.tiles_y;
     int64_t wpi8 = (32768 + g.batch - 1) / g.batch;
     wpi8 = std::max<int64_t>(1, std::min<int64_t>(wpi8, groups8));
@@ -787,7 +746,7 @@ int launch_moments(int kind, int n, int dtype, const void* src, const Geom& g,
     auto go = [&](auto kind_tag) {
       constexpr int K = decltype(kind_tag)::value;
       if (dtype == DT_U8) moments8_mfma<K><<<grid8, t8::kWave, 0, s>>>(p);
-      else moments8_kernel<K, DT_I16><<<grid8, t8::kWave, 0, s>>>(p);
+      else moments8_kernel<K><<<grid8, t8::kWave, 0, s>>>(p);
     };
     switch (kind) {
       case KIND_SIGN: go(std::integral_constant<int, KIND_SIGN>{}); break;
