@@ -97,6 +97,23 @@ def test_moments_extreme_u8_full_groups(kind):
         assert record_matches(mom[i], P.coefficient_moments(im, kind, 8), 8), (i, kind)
 
 
+@pytest.mark.parametrize("kind", M.KINDS + M.COMPARISON_KINDS)
+def test_moments_8bit_narrow_images_and_many_images(kind):
+    """8-bit moments of 8x8 tiles (the matrix-core form): images narrower
+    than one 16-tile step (1, 3 and 17 tiles wide), a single tile row, and a
+    batch of 300 images, where the walking waves per image clamp to the
+    image's one tile group."""
+    for h, w in ((8, 8), (8, 24), (24, 8), (8, 136), (40, 8 * 17)):
+        imgs = [synth.ar1_image(h, w, rho=0.9, seed=900 + i) for i in range(2)]
+        mom = host(adct.moments(to_dev(np.stack(imgs)), kind, 8))
+        for i, im in enumerate(imgs):
+            assert record_matches(mom[i], P.coefficient_moments(im, kind, 8), 8), (h, w, i)
+    imgs = [synth.ar1_image(8, 64, rho=0.5 + 0.001 * i, seed=950 + i) for i in range(300)]
+    mom = host(adct.moments(to_dev(np.stack(imgs)), kind, 8))
+    for i in (0, 1, 150, 299):
+        assert record_matches(mom[i], P.coefficient_moments(imgs[i], kind, 8), 8), i
+
+
 def test_moments_accumulate_over_calls():
     img = synth.ar1_image(64, 256, rho=0.95, seed=11)
     x = to_dev(img)
