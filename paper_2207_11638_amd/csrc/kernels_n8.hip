@@ -157,8 +157,10 @@ hipError_t launch_typed(Mode mode, const PassParams& p_in, hipStream_t s) {
   p.gpw = 1;
   // images interleaved by the fused kernel: wide for small r, where the
   // per-workgroup error-energy atomics queue on one address, narrow for large
-  // r, where the output stream wants raster order (measured on the C1 shape)
-  p.spread = std::min(p.g.batch, p.r <= 16 ? 64 : (p.r <= 45 ? 16 : 2));
+  // r, where the output stream wants raster order (measured per r on the C1
+  // shape: 128 for r <= 10, 64 up to 16, 32 up to 28, 8 up to 45, 1 beyond)
+  p.spread = std::min(p.g.batch,
+                      p.r <= 10 ? 128 : (p.r <= 16 ? 64 : (p.r <= 28 ? 32 : (p.r <= 45 ? 8 : 1))));
   const dim3 grid = grid_for(p.g);
   const bool quant = p.qstep > 0;
   switch (mode) {
