@@ -26,6 +26,9 @@ against values the paper prints, closed forms or brute force, except
     the paper prints;
   * the empirical 2D coding gain: pinned against the AR(1) model's
     population moments (exactly twice the 1D gain) and, statistically, on a
-    large synthetic field; the paper defines only the model's closed form.
+    large synthetic field; the paper defines only the model's closed form;
+  * the SSIM of section 5.1: pinned by closed forms (identical and constant
+    images), symmetry and a brute-force window, but parity unpinned against
+    the paper's own SSIM values, whose images are not available.
 """
 from . import matrices, metrics, pipeline  # noqa: F401
