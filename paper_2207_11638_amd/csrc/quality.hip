@@ -408,8 +408,12 @@ __device__ __forceinline__ uint32_t pack_i8x4(int a, int b, int c, int d) {
          ((static_cast<uint32_t>(c) & 0xffu) << 16) | (static_cast<uint32_t>(d) << 24);
 }
 
+// Five waves per SIMD: the compiler then keeps the accumulators in 90
+// VGPRs (no AGPRs, no spills) instead of 84 + 20, and the extra resident
+// waves keep more pixel rows in flight (0.975 -> 0.83 ms per 4 GiB pass).
 template <int KIND>
-__global__ __launch_bounds__(t8::kWave) void moments8_mfma(MomParams p) {
+__global__ __launch_bounds__(t8::kWave) __attribute__((amdgpu_waves_per_eu(5)))
+void moments8_mfma(MomParams p) {
   using namespace t8;
   constexpr int NN = kN * kN;
   constexpr TransformInfo<8> kInf = make_info<KIND, 8>();
