@@ -411,6 +411,8 @@ __device__ __forceinline__ uint32_t pack_i8x4(int a, int b, int c, int d) {
 // Five waves per SIMD: the compiler then keeps the accumulators in 90
 // VGPRs (no AGPRs, no spills) instead of 84 + 20, and the extra resident
 // waves keep more pixel rows in flight (0.975 -> 0.83 ms per 4 GiB pass).
+// One 4.3 KB fold buffer (sums, then squares) lets LDS hold 36 one-wave
+// workgroups per compute unit, so the registers set the limit (20).
 template <int KIND>
 __global__ __launch_bounds__(t8::kWave) __attribute__((amdgpu_waves_per_eu(5)))
 void moments8_mfma(MomParams p) {
@@ -425,7 +427,7 @@ void moments8_mfma(MomParams p) {
                       : 4ull * 4 * kBmax * kBmax < (1ull << 32) ? 4
                       : 4ull * 2 * kBmax * kBmax < (1ull << 32) ? 2 : 1;
   constexpr int FS = 17;   // LDS stride of a lane's 16 run sums
-  __shared__ int fold[2][kWave * FS];
+  __shared__ int fold[kWave * FS];   // the sums, then the squares
   const TransformInfo<8>& I = info<KIND, 8>();
   const int lane = threadIdx.x;
   const int q = lane >> 4, col = lane & 15;
@@ -470,19 +472,21 @@ void moments8_mfma(MomParams p) {
   const int ph = 16 * ((lane >> 2) & 3);
   auto fold_run = [&]() {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      fold[0][lane * FS + k] = s1r[k >> 2][k & 3];
-      fold[1][lane * FS + k] = static_cast<int>(s2r[k]);
-      s2r[k] = 0;
-    }
+    for (int k = 0; k < 16; ++k) fold[lane * FS + k] = s1r[k >> 2][k & 3];
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk) s1r[blk] = zero;
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      t1 += fold[0][(ph + c) * FS + pk];
-      t2 += static_cast<uint32_t>(fold[1][(ph + c) * FS + pk]);
+    for (int c = 0; c < 16; ++c) t1 += fold[(ph + c) * FS + pk];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      fold[lane * FS + k] = static_cast<int>(s2r[k]);
+      s2r[k] = 0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t2 += static_cast<uint32_t>(fold[(ph + c) * FS + pk]);
     __syncthreads();
   };
 
